@@ -1,0 +1,156 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) library for the fused time step of the
+ * non-orthogonal multiple-relaxation-time lattice Boltzmann method with the
+ * pseudopotential multiphase model of Fei, Du, Luo, Succi, Lauricella, Montessori and
+ * Wang, "Modeling realistic multiphase flows using a non-orthogonal
+ * multiple-relaxation-time lattice Boltzmann method" (arXiv 2306.16274).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Lattice units: dx = dt = c = 1, c_s^2 = 1/3 (Sec. II A).
+ *  - A lattice of nx*ny*nz nodes is indexed n = x + nx*(y + ny*z) (x fastest).
+ *  - Host arrays passed in or out are float64 and owned by the caller. Field arrays hold
+ *    one value per node in that order; vector fields (u) are 3 planes of N values
+ *    (u_x, u_y, u_z); population arrays are Q planes of N values in the velocity order
+ *    of Eq. (1) (D3Q27) or Eq. (C1) (D3Q19: the first 19 of the D3Q27 list).
+ *  - The context owns every device buffer it allocates. A stream given in lbm_params is
+ *    borrowed (never destroyed); with stream == NULL the context creates its own.
+ *  - Populations exchanged through lbm_set_populations / lbm_get_populations are the
+ *    f_bar(x, t) of Sec. II A (after streaming, before collision): rho = sum_i f_bar_i and
+ *    rho u = sum_i f_bar_i e_i + F/2 (Eq. (10)). Solid nodes carry no populations and
+ *    read back as 0.
+ *  - Every call returns an lbm_status; LBM_OK is 0. On error, lbm_last_error() returns
+ *    a context-owned message (valid until the next call on that context).
+ *  - Calls on one context are not thread-safe; distinct contexts are independent.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,      /* bad argument or parameter (message says which)            */
+    LBM_ENOMEM = -2,      /* device or pinned host allocation failed                   */
+    LBM_EDEVICE = -3,     /* a HIP runtime call failed                                 */
+    LBM_ENONFINITE = -4,  /* the periodic health check found a non-finite or negative
+                             density; the state stays readable, further steps refused  */
+    LBM_ESTATE = -5       /* call not allowed in the current state (e.g. step before
+                             initialisation, or after LBM_ENONFINITE)                   */
+} lbm_status;
+
+enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16 = 2 };       /* population storage type   */
+enum { LBM_EOS_CS = 0, LBM_EOS_PIECEWISE = 1 };          /* equation of state         */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1 };           /* per domain face           */
+
+/*
+ * Problem statement. Defaults (lbm_params_default) follow Sec. II B: s0 = s1 = 1,
+ * s2b = s3b = 0.6, all other non-viscous rates 1.2; G = -1 (Sec. III A); sigma = 0.1
+ * (Sec. III A); kappa = 0; G_ads = 0 (neutral wall, Sec. III E).
+ */
+typedef struct {
+    int32_t lattice;          /* 19 (D3Q19, Appendix C) or 27 (D3Q27, Sec. II A-B)        */
+    int32_t storage;          /* LBM_FP64: stored and computed in float64.
+                                 LBM_FP32 / LBM_FP16: stored as deviations
+                                 f_i - w_i*rho_ref, computed in float32                 */
+    int32_t nx, ny, nz;       /* lattice size, each >= 1                                 */
+    int32_t eos;              /* LBM_EOS_CS or LBM_EOS_PIECEWISE                         */
+    double rho_ref;           /* shift of the stored populations (0 = plain storage)     */
+    /* Carnahan-Starling: p = rho R T (1+eta+eta^2-eta^3)/(1-eta)^3 - a rho^2,
+       eta = b rho / 4, T = T_over_Tc * 0.3773 a / (b R)                                 */
+    double cs_a, cs_b, cs_R, T_over_Tc;
+    /* Piecewise-linear EOS, Eq. (18): slopes and the two spinodal densities             */
+    double pw_theta_v, pw_theta_m, pw_theta_l, pw_rho1, pw_rho2;
+    double G;                 /* interaction strength of Eq. (16)                        */
+    double sigma;             /* mechanical-stability parameter of Eq. (B1)              */
+    double kappa;             /* surface-tension tuning of Eq. (B2)                      */
+    double G_ads;             /* fluid-solid interaction strength of Eq. (22)            */
+    double nu_l, nu_v;        /* kinematic viscosity; nu_v != nu_l enables Eq. (24)      */
+    double rho_l, rho_v;      /* densities anchoring the linear nu(rho) of Eq. (24)      */
+    double s0, s1, s2b, s3, s3b, s4, s4b, s5, s6;   /* rates of Eq. (12) / Eq. (C3);
+                                 s_nu (s2) follows from nu: nu = (1/s_nu - 1/2)/3          */
+    int32_t bc[3][2];         /* [axis x,y,z][lo,hi]: LBM_BC_WALL makes the node layer
+                                 at index 0 (lo) or n-1 (hi) solid; neighbours always
+                                 wrap periodically, so a wall-free axis is periodic     */
+    int32_t cylinder;         /* nonzero: solid x-aligned cylinder                       */
+    double cyl_y, cyl_z, cyl_r;   /* solid where (y-cyl_y)^2 + (z-cyl_z)^2 <= cyl_r^2    */
+    double body_force[3];     /* uniform body force added to F (default 0)               */
+    void* stream;             /* hipStream_t to enqueue on, or NULL                      */
+    int32_t reduce_every;     /* health check cadence in steps (0 = never)               */
+    int32_t reserved;
+} lbm_params;
+
+/* Fill *p with the defaults above (D3Q19, FP32, 64^3, CS EOS at T = 0.7 T_c, a = 0.5,
+   b = 4, R = 1, nu = 0.1, fully periodic, rho_ref = 0). Returns LBM_EINVAL on NULL.    */
+lbm_status lbm_params_default(lbm_params* p);
+
+/* Validate *p, allocate the lattice on the current HIP device and return a context in
+   *out. Rejects: lattice not 19/27, sizes < 1, rates outside (0,2), nu <= 0, an EOS
+   without a two-phase region, a cylinder that covers the domain. The populations are
+   undefined until one of the lbm_init_* / lbm_set_populations calls.                  */
+lbm_status lbm_create(const lbm_params* p, lbm_ctx** out);
+
+/* Free everything the context owns. NULL is accepted.                                 */
+lbm_status lbm_destroy(lbm_ctx* c);
+
+/* Message of the last failed call on c (or of the last failed lbm_create if c == NULL).*/
+const char* lbm_last_error(const lbm_ctx* c);
+
+/* Initial state f_bar = M^-1 m^eq(rho0, u0) (Sec. II B) of a droplet centred at
+   (cx, cy, cz) with radius R: rho0 = (rho_in+rho_out)/2 - (rho_in-rho_out)/2
+   tanh(2 (r - R)/W), the radial form of the interface profile of Eq. (21). The velocity
+   (ux, uy, uz) is carried by the liquid fraction clamp((rho0-rho_out)/(rho_in-rho_out),
+   0, 1) of the noise-free profile. Inside |r - R| < W the density is multiplied by
+   1 + noise_amp (2 U_n - 1), U_n the SplitMix64 uniform of node n under seed. Resets the
+   step counter and the health flag. Asynchronous on the context stream.               */
+lbm_status lbm_init_droplet(lbm_ctx* c, double cx, double cy, double cz, double R, double W,
+                            double rho_in, double rho_out, double ux, double uy, double uz,
+                            double noise_amp, uint64_t seed);
+
+/* Initial state f_bar = M^-1 m^eq(rho, u) from host fields: rho (N values) and u
+   (3 planes of N, or NULL for rest). Values at solid nodes are ignored. Synchronous.  */
+lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* u);
+
+/* Replace / read the state f_bar(x, t) (Q planes of N float64, host memory).
+   Synchronous. Set rounds to the storage type.                                        */
+lbm_status lbm_set_populations(lbm_ctx* c, const double* f);
+lbm_status lbm_get_populations(lbm_ctx* c, double* f);
+
+/* Advance nsteps time steps (Sec. II A: streaming with halfway bounce-back, rho and psi,
+   F_int of Eq. (16), F_ads of Eq. (22), Q_ab of Eq. (B2), the moment-space collision of
+   Eq. (8) with the forcing moments of Eq. (B1), f_bar* = M^-1 m*). Enqueues on the
+   context stream and returns without waiting, except every reduce_every steps, where the
+   result of the previous health check is read. nsteps >= 0.                          */
+lbm_status lbm_step(lbm_ctx* c, int64_t nsteps);
+
+/* Number of time steps taken since the last initialisation.                           */
+int64_t lbm_steps_done(const lbm_ctx* c);
+
+/* Macroscopic fields at the current time (after streaming, before collision):
+   rho = sum f_bar, u = (sum f_bar e + F/2)/rho (Eq. (10)), p = rho/3 + G psi^2/2
+   (Eq. (17)). Any output pointer may be NULL. totals (5 values) receives the float64
+   sums over fluid nodes of rho, rho u_x, rho u_y, rho u_z and rho |u|^2 / 2. Solid nodes
+   read 0. Synchronous.                                                                 */
+lbm_status lbm_moments(lbm_ctx* c, double* rho, double* u, double* p, double* totals);
+
+/* Wait for all work enqueued on the context stream.                                   */
+lbm_status lbm_synchronize(lbm_ctx* c);
+
+/* Coexistence densities (Maxwell equal-area construction, the conditions of Eq. (19))
+   of the equation of state described by *p. Host-only.                                 */
+lbm_status lbm_coexistence(const lbm_params* p, double* rho_v, double* rho_l);
+
+/* Device bytes a context created from *p allocates (for admission control), or -1.    */
+int64_t lbm_footprint_bytes(const lbm_params* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */
