@@ -1,0 +1,608 @@
+// Host side of the C ABI declared in include/lbm.h: parameter validation, device
+// buffers, kernel dispatch over (lattice, storage type, solid/no-solid) and the host-only
+// coexistence solver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "kernels.h"
+
+using namespace lbmk;
+
+struct lbm_ctx {
+    lbm_params p{};
+    int device = 0;
+    int Q = 19;
+    long long N = 0, stride = 0;
+    size_t elem = 4;               // bytes per stored population
+    void* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    void* psi = nullptr;           // float64 (FP64 storage) or float32
+    uint8_t* solid = nullptr;
+    bool any_solid = false;
+    double* mom = nullptr;         // rho, u (3), p: 5 N doubles, allocated on first use
+    double* partial = nullptr;     // per-block partial sums (moments and health check)
+    long long partial_cap = 0;
+    double* dtot = nullptr;        // 5 device doubles
+    double* hhealth = nullptr;     // pinned: [min rho, non-finite flag]
+    hipEvent_t health_ev = nullptr;
+    bool health_pending = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool initialised = false;
+    bool failed = false;
+    int64_t steps = 0;
+    Phys<double> pd{};
+    Phys<float> pf{};
+    std::string err;
+};
+
+static std::string g_create_error;
+
+static lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf; else g_create_error = buf;
+    return s;
+}
+
+#define HIPCHK(c, call)                                                                  \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail((c), e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,       \
+                        "%s failed: %s", #call, hipGetErrorString(e_));                  \
+    } while (0)
+
+// ---------------------------------------------------------------------------------------
+// Equations of state on the host (float64), for validation and the coexistence solver.
+static double eos_p(const lbm_params& p, double rho) {
+    if (p.eos == LBM_EOS_CS) {
+        const double T = p.T_over_Tc * 0.3773 * p.cs_a / (p.cs_b * p.cs_R);
+        const double eta = p.cs_b * rho / 4.0, om = 1.0 - eta;
+        return rho * p.cs_R * T * (1 + eta + eta * eta - eta * eta * eta) / (om * om * om) -
+               p.cs_a * rho * rho;
+    }
+    const double p1 = p.pw_rho1 * p.pw_theta_v;
+    const double p2 = p1 + (p.pw_rho2 - p.pw_rho1) * p.pw_theta_m;
+    if (rho <= p.pw_rho1) return rho * p.pw_theta_v;
+    if (rho <= p.pw_rho2) return p1 + (rho - p.pw_rho1) * p.pw_theta_m;
+    return p2 + (rho - p.pw_rho2) * p.pw_theta_l;
+}
+
+static double eos_rho_max(const lbm_params& p) {
+    return p.eos == LBM_EOS_CS ? 0.999 * 4.0 / p.cs_b : 50.0;
+}
+
+// integral of p(rho)/rho^2 over [a, b] with composite 8-point Gauss-Legendre in ln(rho)
+static double int_p_over_rho2(const lbm_params& p, double a, double b) {
+    static const double xg[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267,
+                                 0.9602898564975363};
+    static const double wg[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745,
+                                 0.1012285362903763};
+    const double la = std::log(a), lb = std::log(b);
+    const int panels = 400;
+    const double hw = (lb - la) / panels;
+    double s = 0;
+    for (int k = 0; k < panels; ++k) {
+        const double mid = la + (k + 0.5) * hw;
+        for (int j = 0; j < 4; ++j)
+            for (int sg = -1; sg <= 1; sg += 2) {
+                const double t = mid + sg * xg[j] * 0.5 * hw;
+                const double r = std::exp(t);
+                s += wg[j] * 0.5 * hw * eos_p(p, r) / r;
+            }
+    }
+    return s;
+}
+
+extern "C" lbm_status lbm_coexistence(const lbm_params* pp, double* rho_v, double* rho_l) {
+    if (!pp || !rho_v || !rho_l) return fail(nullptr, LBM_EINVAL, "null argument");
+    const lbm_params& p = *pp;
+    const double hi = eos_rho_max(p), lo = 1e-9;
+    // spinodals: scan dp/drho for the unstable branch
+    const int M = 200000;
+    auto dp = [&](double r) { const double h = 1e-7 * std::max(r, 1e-6);
+                              return (eos_p(p, r + h) - eos_p(p, r - h)) / (2 * h); };
+    double s_lo = -1, s_hi = -1, prev = dp(lo);
+    double rprev = lo;
+    for (int k = 1; k <= M; ++k) {
+        const double r = lo + (hi - lo) * k / M;
+        const double v = dp(r);
+        if (prev >= 0 && v < 0 && s_lo < 0) s_lo = 0.5 * (r + rprev);
+        if (prev < 0 && v >= 0) s_hi = 0.5 * (r + rprev);
+        prev = v; rprev = r;
+    }
+    if (s_lo < 0 || s_hi < 0)
+        return fail(nullptr, LBM_EINVAL, "equation of state has no two-phase region");
+    const double pmax = eos_p(p, s_lo), pmin = std::max(eos_p(p, s_hi), eos_p(p, lo));
+    auto root = [&](double p0, double a, double b) {   // p(r) = p0 on a monotone branch
+        double fa = eos_p(p, a) - p0;
+        for (int it = 0; it < 200; ++it) {
+            const double m = 0.5 * (a + b), fm = eos_p(p, m) - p0;
+            if ((fm < 0) == (fa < 0)) { a = m; fa = fm; } else b = m;
+        }
+        return 0.5 * (a + b);
+    };
+    auto area = [&](double p0, double* rv, double* rl) {
+        *rv = root(p0, lo, s_lo);
+        *rl = root(p0, hi, s_hi);
+        return p0 * (1.0 / *rl - 1.0 / *rv) + int_p_over_rho2(p, *rv, *rl);
+    };
+    double a = pmin + 1e-12 * std::fabs(pmax), b = pmax - 1e-12 * std::fabs(pmax), rv, rl;
+    double fa = area(a, &rv, &rl);
+    for (int it = 0; it < 200; ++it) {
+        const double m = 0.5 * (a + b), fm = area(m, &rv, &rl);
+        if ((fm < 0) == (fa < 0)) { a = m; fa = fm; } else b = m;
+        if (b - a < 1e-17) break;
+    }
+    area(0.5 * (a + b), &rv, &rl);
+    *rho_v = rv; *rho_l = rl;
+    return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+extern "C" lbm_status lbm_params_default(lbm_params* p) {
+    if (!p) return LBM_EINVAL;
+    std::memset(p, 0, sizeof *p);
+    p->lattice = 19; p->storage = LBM_FP32;
+    p->nx = p->ny = p->nz = 64;
+    p->eos = LBM_EOS_CS;
+    p->cs_a = 0.5; p->cs_b = 4.0; p->cs_R = 1.0; p->T_over_Tc = 0.7;
+    p->pw_theta_v = 1.0 / 6.0; p->pw_theta_m = -1.0 / 120.0; p->pw_theta_l = 1.0 / 3.0;
+    p->pw_rho1 = 0.0013246030524; p->pw_rho2 = 0.9758004064415;
+    p->G = -1.0; p->sigma = 0.1; p->kappa = 0.0; p->G_ads = 0.0;
+    p->nu_l = p->nu_v = 0.1; p->rho_l = 1.0; p->rho_v = 0.001;
+    p->s0 = 1.0; p->s1 = 1.0; p->s2b = 0.6; p->s3 = 1.2; p->s3b = 0.6;
+    p->s4 = 1.2; p->s4b = 1.2; p->s5 = 1.2; p->s6 = 1.2;
+    return LBM_OK;
+}
+
+static long long plane_stride(long long N) { return (N + 63) / 64 * 64; }
+
+static size_t storage_bytes(int storage) {
+    return storage == LBM_FP64 ? 8 : storage == LBM_FP32 ? 4 : 2;
+}
+
+extern "C" int64_t lbm_footprint_bytes(const lbm_params* p) {
+    if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1) return -1;
+    const long long N = (long long)p->nx * p->ny * p->nz;
+    const int Q = p->lattice == 27 ? 27 : 19;
+    const size_t b = storage_bytes(p->storage);
+    const size_t r = p->storage == LBM_FP64 ? 8 : 4;
+    return (int64_t)(2 * Q * plane_stride(N) * b + N * r + N);
+}
+
+template <typename R>
+static Phys<R> make_phys(const lbm_params& p) {
+    Phys<R> P{};
+    P.rho_ref = (R)p.rho_ref;
+    P.G = (R)p.G; P.two_over_G = (R)(2.0 / p.G);
+    P.sigma = (R)p.sigma; P.kappa = (R)p.kappa; P.G_ads = (R)p.G_ads;
+    P.eos = p.eos == LBM_EOS_CS ? EOS_CS : EOS_PIECEWISE;
+    P.cs_a = (R)p.cs_a; P.cs_b = (R)p.cs_b;
+    P.cs_RT = (R)(p.cs_R * p.T_over_Tc * 0.3773 * p.cs_a / (p.cs_b * p.cs_R));
+    P.pw_tv = (R)p.pw_theta_v; P.pw_tm = (R)p.pw_theta_m; P.pw_tl = (R)p.pw_theta_l;
+    P.pw_r1 = (R)p.pw_rho1; P.pw_r2 = (R)p.pw_rho2;
+    const double p1 = p.pw_rho1 * p.pw_theta_v;
+    P.pw_p1 = (R)p1; P.pw_p2 = (R)(p1 + (p.pw_rho2 - p.pw_rho1) * p.pw_theta_m);
+    P.s_nu = (R)(1.0 / (3.0 * p.nu_l + 0.5));
+    P.s_e = (R)p.s2b; P.s3 = (R)p.s3; P.s3b = (R)p.s3b; P.s4 = (R)p.s4; P.s4b = (R)p.s4b;
+    P.s5 = (R)p.s5; P.s6 = (R)p.s6;
+    P.var_nu = p.nu_v != p.nu_l;
+    P.nu_v = (R)p.nu_v; P.rho_v = (R)p.rho_v;
+    P.dnu_drho = P.var_nu ? (R)((p.nu_l - p.nu_v) / (p.rho_l - p.rho_v)) : R(0);
+    P.bfx = (R)p.body_force[0]; P.bfy = (R)p.body_force[1]; P.bfz = (R)p.body_force[2];
+    return P;
+}
+
+static bool rate_ok(double s) { return s > 0.0 && s < 2.0 && std::isfinite(s); }
+
+static lbm_status validate(const lbm_params& p) {
+    if (p.lattice != 19 && p.lattice != 27) return fail(nullptr, LBM_EINVAL, "lattice must be 19 or 27");
+    if (p.storage < LBM_FP64 || p.storage > LBM_FP16) return fail(nullptr, LBM_EINVAL, "unknown storage type");
+    if (p.nx < 1 || p.ny < 1 || p.nz < 1) return fail(nullptr, LBM_EINVAL, "lattice sizes must be >= 1");
+    const long long N = (long long)p.nx * p.ny * p.nz;
+    if (N > 0x7fffffffLL) return fail(nullptr, LBM_EINVAL, "more than 2^31-1 nodes");
+    if (p.nz > 65535 || p.ny > 65535 * 4) return fail(nullptr, LBM_EINVAL, "nz above 65535");
+    if (p.eos != LBM_EOS_CS && p.eos != LBM_EOS_PIECEWISE) return fail(nullptr, LBM_EINVAL, "unknown eos");
+    if (!(p.G < 0.0)) return fail(nullptr, LBM_EINVAL, "G must be negative (attractive)");
+    if (p.eos == LBM_EOS_CS && !(p.cs_a > 0 && p.cs_b > 0 && p.cs_R > 0 && p.T_over_Tc > 0))
+        return fail(nullptr, LBM_EINVAL, "Carnahan-Starling a, b, R, T must be positive");
+    if (p.eos == LBM_EOS_PIECEWISE &&
+        !(p.pw_theta_v > 0 && p.pw_theta_l > 0 && p.pw_theta_m < 0 && p.pw_rho1 > 0 && p.pw_rho2 > p.pw_rho1))
+        return fail(nullptr, LBM_EINVAL, "piecewise EOS needs theta_v, theta_l > 0 > theta_m and 0 < rho1 < rho2");
+    if (!(p.nu_l > 0) || !(p.nu_v > 0)) return fail(nullptr, LBM_EINVAL, "viscosities must be positive");
+    if (p.nu_v != p.nu_l && !(p.rho_l != p.rho_v)) return fail(nullptr, LBM_EINVAL, "rho_l == rho_v with nu_l != nu_v");
+    const double rates[] = {p.s2b, p.s3, p.s3b, p.s4, p.s4b, p.s5, p.s6, 1.0 / (3 * p.nu_l + 0.5),
+                            1.0 / (3 * p.nu_v + 0.5)};
+    for (double s : rates)
+        if (!rate_ok(s)) return fail(nullptr, LBM_EINVAL, "relaxation rate %g outside (0, 2)", s);
+    for (int a = 0; a < 3; ++a)
+        for (int s = 0; s < 2; ++s)
+            if (p.bc[a][s] != LBM_BC_PERIODIC && p.bc[a][s] != LBM_BC_WALL)
+                return fail(nullptr, LBM_EINVAL, "unknown boundary condition");
+    if (p.reduce_every < 0) return fail(nullptr, LBM_EINVAL, "reduce_every must be >= 0");
+    return LBM_OK;
+}
+
+static void build_solid(const lbm_params& p, std::vector<uint8_t>& s, bool& any) {
+    const long long N = (long long)p.nx * p.ny * p.nz;
+    s.assign(N, 0);
+    any = false;
+    for (int z = 0; z < p.nz; ++z)
+        for (int y = 0; y < p.ny; ++y)
+            for (int x = 0; x < p.nx; ++x) {
+                bool sol = false;
+                const int c[3] = {x, y, z}, n[3] = {p.nx, p.ny, p.nz};
+                for (int a = 0; a < 3; ++a) {
+                    if (p.bc[a][0] == LBM_BC_WALL && c[a] == 0) sol = true;
+                    if (p.bc[a][1] == LBM_BC_WALL && c[a] == n[a] - 1) sol = true;
+                }
+                if (p.cylinder) {
+                    const double dy = y - p.cyl_y, dz = z - p.cyl_z;
+                    if (dy * dy + dz * dz <= p.cyl_r * p.cyl_r) sol = true;
+                }
+                if (sol) { s[x + (long long)p.nx * (y + (long long)p.ny * z)] = 1; any = true; }
+            }
+}
+
+static void free_all(lbm_ctx* c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    for (void* b : c->f) if (b) hipFree(b);
+    if (c->psi) hipFree(c->psi);
+    if (c->solid) hipFree(c->solid);
+    if (c->mom) hipFree(c->mom);
+    if (c->partial) hipFree(c->partial);
+    if (c->dtot) hipFree(c->dtot);
+    if (c->hhealth) hipHostFree(c->hhealth);
+    if (c->health_ev) hipEventDestroy(c->health_ev);
+    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+}
+
+extern "C" lbm_status lbm_create(const lbm_params* pp, lbm_ctx** out) {
+    if (!pp || !out) return fail(nullptr, LBM_EINVAL, "null argument");
+    *out = nullptr;
+    lbm_status st = validate(*pp);
+    if (st != LBM_OK) return st;
+    double rv, rl;
+    if (lbm_coexistence(pp, &rv, &rl) != LBM_OK)
+        return fail(nullptr, LBM_EINVAL, "equation of state has no two-phase region");
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(nullptr, LBM_ENOMEM, "host allocation failed");
+    c->p = *pp;
+    c->Q = pp->lattice;
+    c->N = (long long)pp->nx * pp->ny * pp->nz;
+    c->stride = plane_stride(c->N);
+    c->elem = storage_bytes(pp->storage);
+    c->pd = make_phys<double>(*pp);
+    c->pf = make_phys<float>(*pp);
+    auto bail = [&](lbm_status s) { g_create_error = c->err; free_all(c); delete c; return s; };
+#define CHK(call) do { hipError_t e_ = (call); if (e_ != hipSuccess) {                     \
+        fail(c, e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "%s failed: %s", #call, \
+             hipGetErrorString(e_));                                                      \
+        return bail(e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE); } } while (0)
+    CHK(hipGetDevice(&c->device));
+    if (pp->stream) c->stream = (hipStream_t)pp->stream;
+    else { CHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)); c->own_stream = true; }
+    const size_t fbytes = (size_t)c->Q * c->stride * c->elem;
+    CHK(hipMalloc(&c->f[0], fbytes));
+    CHK(hipMalloc(&c->f[1], fbytes));
+    CHK(hipMemsetAsync(c->f[0], 0, fbytes, c->stream));
+    CHK(hipMemsetAsync(c->f[1], 0, fbytes, c->stream));
+    CHK(hipMalloc(&c->psi, (size_t)c->N * (pp->storage == LBM_FP64 ? 8 : 4)));
+    CHK(hipMalloc(&c->solid, (size_t)c->N));
+    std::vector<uint8_t> s;
+    build_solid(*pp, s, c->any_solid);
+    long long nfluid = 0;
+    for (uint8_t v : s) nfluid += !v;
+    if (nfluid == 0) { fail(c, LBM_EINVAL, "geometry leaves no fluid node"); return bail(LBM_EINVAL); }
+    CHK(hipMemcpyAsync(c->solid, s.data(), (size_t)c->N, hipMemcpyHostToDevice, c->stream));
+    CHK(hipMalloc(&c->dtot, 8 * sizeof(double)));
+    CHK(hipHostMalloc((void**)&c->hhealth, 2 * sizeof(double), hipHostMallocDefault));
+    CHK(hipEventCreateWithFlags(&c->health_ev, hipEventDisableTiming));
+    CHK(hipStreamSynchronize(c->stream));
+#undef CHK
+    *out = c;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_destroy(lbm_ctx* c) {
+    if (!c) return LBM_OK;
+    free_all(c);
+    delete c;
+    return LBM_OK;
+}
+
+extern "C" const char* lbm_last_error(const lbm_ctx* c) {
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+extern "C" int64_t lbm_steps_done(const lbm_ctx* c) { return c ? c->steps : -1; }
+
+// ---------------------------------------------------------------------------------------
+// Launch helpers
+struct Launch { dim3 grid, block; };
+static Launch node_launch(const lbm_ctx* c) {
+    Launch L;
+    const int bx = c->p.nx >= 64 ? 64 : (c->p.nx >= 32 ? 32 : 16);
+    const int by = 256 / bx;
+    L.block = dim3(bx, by, 1);
+    L.grid = dim3((c->p.nx + bx - 1) / bx, (c->p.ny + by - 1) / by, c->p.nz);
+    return L;
+}
+static long long nblocks(const Launch& L) { return (long long)L.grid.x * L.grid.y * L.grid.z; }
+
+static Grid grid_of(const lbm_ctx* c) {
+    Grid g;
+    g.nx = c->p.nx; g.ny = c->p.ny; g.nz = c->p.nz; g.stride = c->stride;
+    return g;
+}
+
+static lbm_status ensure_partial(lbm_ctx* c, long long n) {
+    if (c->partial_cap >= n) return LBM_OK;
+    if (c->partial) { HIPCHK(c, hipStreamSynchronize(c->stream)); hipFree(c->partial); c->partial = nullptr; }
+    HIPCHK(c, hipMalloc(&c->partial, (size_t)n * sizeof(double)));
+    c->partial_cap = n;
+    return LBM_OK;
+}
+
+template <int Q, typename T>
+static void launch_psi(lbm_ctx* c, const void* fin) {
+    using R = typename Arith<T>::type;
+    const Launch L = node_launch(c);
+    const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
+                                                         ? (const void*)&c->pd : (const void*)&c->pf);
+    if (c->any_solid)
+        hipLaunchKernelGGL((k_density_psi<Q, T, true>), L.grid, L.block, 0, c->stream,
+                           (const T*)fin, c->solid, (R*)c->psi, grid_of(c), P);
+    else
+        hipLaunchKernelGGL((k_density_psi<Q, T, false>), L.grid, L.block, 0, c->stream,
+                           (const T*)fin, c->solid, (R*)c->psi, grid_of(c), P);
+}
+
+template <int Q, typename T>
+static void launch_collide(lbm_ctx* c, const void* fin, void* fout) {
+    using R = typename Arith<T>::type;
+    const Launch L = node_launch(c);
+    const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
+                                                         ? (const void*)&c->pd : (const void*)&c->pf);
+    hipLaunchKernelGGL((k_collide<Q, T>), L.grid, L.block, 0, c->stream, (const T*)fin, (T*)fout,
+                       (const R*)c->psi, grid_of(c), P);
+}
+
+// Dispatch a templated functor over (Q, storage type).
+template <template <int, typename> class Fn, typename... A>
+static lbm_status dispatch(lbm_ctx* c, A... args) {
+    if (c->Q == 19) {
+        if (c->p.storage == LBM_FP64) return Fn<19, double>::run(c, args...);
+        if (c->p.storage == LBM_FP32) return Fn<19, float>::run(c, args...);
+        return Fn<19, _Float16>::run(c, args...);
+    }
+    if (c->p.storage == LBM_FP64) return Fn<27, double>::run(c, args...);
+    if (c->p.storage == LBM_FP32) return Fn<27, float>::run(c, args...);
+    return Fn<27, _Float16>::run(c, args...);
+}
+
+template <int Q, typename T>
+struct StepFn {
+    static lbm_status run(lbm_ctx* c, int64_t nsteps) {
+        for (int64_t s = 0; s < nsteps; ++s) {
+            launch_psi<Q, T>(c, c->f[c->cur]);
+            launch_collide<Q, T>(c, c->f[c->cur], c->f[1 - c->cur]);
+            c->cur = 1 - c->cur;
+            c->steps++;
+            if (c->p.reduce_every > 0 && c->steps % c->p.reduce_every == 0) {
+                using R = typename Arith<T>::type;
+                const Launch L = node_launch(c);
+                lbm_status st = ensure_partial(c, 2 * nblocks(L));
+                if (st != LBM_OK) return st;
+                hipLaunchKernelGGL((k_health<Q, T>), L.grid, L.block, 0, c->stream,
+                                   (const T*)c->f[c->cur], (const R*)c->psi, c->partial,
+                                   grid_of(c), c->p.rho_ref);
+                hipLaunchKernelGGL(k_health_final, dim3(1), dim3(256), 0, c->stream,
+                                   c->partial, nblocks(L), c->dtot + 5);
+                HIPCHK(c, hipMemcpyAsync(c->hhealth, c->dtot + 5, 2 * sizeof(double),
+                                         hipMemcpyDeviceToHost, c->stream));
+                HIPCHK(c, hipEventRecord(c->health_ev, c->stream));
+                c->health_pending = true;
+            }
+        }
+        HIPCHK(c, hipGetLastError());
+        return LBM_OK;
+    }
+};
+
+// Read the last health check if it has completed (wait = block until it has).
+static lbm_status poll_health(lbm_ctx* c, bool wait) {
+    if (!c->health_pending) return LBM_OK;
+    if (wait) HIPCHK(c, hipEventSynchronize(c->health_ev));
+    else if (hipEventQuery(c->health_ev) != hipSuccess) return LBM_OK;
+    c->health_pending = false;
+    if (c->hhealth[1] != 0.0 || !(c->hhealth[0] > 0.0)) {
+        c->failed = true;
+        return fail(c, LBM_ENONFINITE, "non-finite or non-positive density detected (min rho %g)",
+                    c->hhealth[0]);
+    }
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    if (nsteps < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
+    if (!c->initialised) return fail(c, LBM_ESTATE, "populations not initialised");
+    if (c->failed) return fail(c, LBM_ESTATE, "a previous health check failed");
+    HIPCHK(c, hipSetDevice(c->device));
+    lbm_status st = poll_health(c, false);
+    if (st != LBM_OK) return st;
+    return dispatch<StepFn>(c, nsteps);
+}
+
+extern "C" lbm_status lbm_synchronize(lbm_ctx* c) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return poll_health(c, true);
+}
+
+// ---------------------------------------------------------------------------------------
+template <int Q, typename T>
+struct InitFieldsFn {
+    static lbm_status run(lbm_ctx* c, const double* drho, const double* du) {
+        using R = typename Arith<T>::type;
+        const Launch L = node_launch(c);
+        const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
+                                                             ? (const void*)&c->pd : (const void*)&c->pf);
+        c->cur = 0;
+        hipLaunchKernelGGL((k_init_fields<Q, T>), L.grid, L.block, 0, c->stream, drho, du,
+                           (T*)c->f[0], c->solid, grid_of(c), P);
+        HIPCHK(c, hipGetLastError());
+        return LBM_OK;
+    }
+};
+
+static lbm_status ensure_mom(lbm_ctx* c) {
+    if (c->mom) return LBM_OK;
+    HIPCHK(c, hipMalloc(&c->mom, (size_t)5 * c->N * sizeof(double)));
+    return LBM_OK;
+}
+
+static void reset_state(lbm_ctx* c) {
+    c->initialised = true;
+    c->failed = false;
+    c->health_pending = false;
+    c->steps = 0;
+}
+
+extern "C" lbm_status lbm_init_droplet(lbm_ctx* c, double cx, double cy, double cz, double R,
+                                       double W, double rho_in, double rho_out, double ux,
+                                       double uy, double uz, double noise_amp, uint64_t seed) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    if (!(W > 0) || !(R >= 0) || !(rho_in > 0) || !(rho_out > 0) || rho_in == rho_out)
+        return fail(c, LBM_EINVAL, "need W > 0, R >= 0, rho_in, rho_out > 0 and distinct");
+    HIPCHK(c, hipSetDevice(c->device));
+    lbm_status st = ensure_mom(c);
+    if (st != LBM_OK) return st;
+    const Launch L = node_launch(c);
+    double* rho0 = c->mom;
+    double* u0 = c->mom + c->N;
+    hipLaunchKernelGGL(k_droplet_fields, L.grid, L.block, 0, c->stream, rho0, u0, grid_of(c), cx,
+                       cy, cz, R, W, rho_in, rho_out, ux, uy, uz, noise_amp, seed);
+    st = dispatch<InitFieldsFn>(c, (const double*)rho0, (const double*)u0);
+    if (st != LBM_OK) return st;
+    reset_state(c);
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* u) {
+    if (!c || !rho) return fail(c, LBM_EINVAL, "null argument");
+    HIPCHK(c, hipSetDevice(c->device));
+    lbm_status st = ensure_mom(c);
+    if (st != LBM_OK) return st;
+    HIPCHK(c, hipMemcpyAsync(c->mom, rho, c->N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if (u) HIPCHK(c, hipMemcpyAsync(c->mom + c->N, u, 3 * c->N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    st = dispatch<InitFieldsFn>(c, (const double*)c->mom, (const double*)(u ? c->mom + c->N : nullptr));
+    if (st != LBM_OK) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    reset_state(c);
+    return LBM_OK;
+}
+
+template <int Q, typename T>
+struct PopFn {
+    static lbm_status run(lbm_ctx* c, double* host, bool set) {
+        double* dbuf = nullptr;
+        const size_t bytes = (size_t)Q * c->N * sizeof(double);
+        HIPCHK(c, hipMalloc(&dbuf, bytes));
+        const Launch L = node_launch(c);
+        hipError_t e = hipSuccess;
+        if (set) {
+            e = hipMemcpyAsync(dbuf, host, bytes, hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) {
+                c->cur = 0;
+                hipLaunchKernelGGL((k_scatter<Q, T>), L.grid, L.block, 0, c->stream, dbuf,
+                                   (T*)c->f[0], c->solid, grid_of(c), c->p.rho_ref);
+                e = hipGetLastError();
+            }
+        } else {
+            hipLaunchKernelGGL((k_gather_out<Q, T>), L.grid, L.block, 0, c->stream,
+                               (const T*)c->f[c->cur], dbuf, c->solid, grid_of(c), c->p.rho_ref);
+            e = hipGetLastError();
+            if (e == hipSuccess) e = hipMemcpyAsync(host, dbuf, bytes, hipMemcpyDeviceToHost, c->stream);
+        }
+        hipError_t e2 = hipStreamSynchronize(c->stream);
+        hipFree(dbuf);
+        if (e != hipSuccess || e2 != hipSuccess)
+            return fail(c, LBM_EDEVICE, "population transfer failed: %s",
+                        hipGetErrorString(e != hipSuccess ? e : e2));
+        return LBM_OK;
+    }
+};
+
+extern "C" lbm_status lbm_set_populations(lbm_ctx* c, const double* f) {
+    if (!c || !f) return fail(c, LBM_EINVAL, "null argument");
+    HIPCHK(c, hipSetDevice(c->device));
+    lbm_status st = dispatch<PopFn>(c, const_cast<double*>(f), true);
+    if (st == LBM_OK) reset_state(c);
+    return st;
+}
+
+extern "C" lbm_status lbm_get_populations(lbm_ctx* c, double* f) {
+    if (!c || !f) return fail(c, LBM_EINVAL, "null argument");
+    if (!c->initialised) return fail(c, LBM_ESTATE, "populations not initialised");
+    HIPCHK(c, hipSetDevice(c->device));
+    return dispatch<PopFn>(c, f, false);
+}
+
+template <int Q, typename T>
+struct MomentsFn {
+    static lbm_status run(lbm_ctx* c, double* rho, double* u, double* p, double* totals) {
+        using R = typename Arith<T>::type;
+        lbm_status st = ensure_mom(c);
+        if (st != LBM_OK) return st;
+        const Launch L = node_launch(c);
+        st = ensure_partial(c, 5 * nblocks(L));
+        if (st != LBM_OK) return st;
+        const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
+                                                             ? (const void*)&c->pd : (const void*)&c->pf);
+        launch_psi<Q, T>(c, c->f[c->cur]);
+        double* drho = c->mom;
+        double* du = c->mom + c->N;
+        double* dp = c->mom + 4 * c->N;
+        hipLaunchKernelGGL((k_moments<Q, T>), L.grid, L.block, 0, c->stream,
+                           (const T*)c->f[c->cur], (const R*)c->psi, drho, du, dp, c->partial,
+                           grid_of(c), P);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, c->stream, c->partial,
+                           nblocks(L), c->dtot);
+        HIPCHK(c, hipGetLastError());
+        const size_t nb = c->N * sizeof(double);
+        if (rho) HIPCHK(c, hipMemcpyAsync(rho, drho, nb, hipMemcpyDeviceToHost, c->stream));
+        if (u) HIPCHK(c, hipMemcpyAsync(u, du, 3 * nb, hipMemcpyDeviceToHost, c->stream));
+        if (p) HIPCHK(c, hipMemcpyAsync(p, dp, nb, hipMemcpyDeviceToHost, c->stream));
+        if (totals) HIPCHK(c, hipMemcpyAsync(totals, c->dtot, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return LBM_OK;
+    }
+};
+
+extern "C" lbm_status lbm_moments(lbm_ctx* c, double* rho, double* u, double* p, double* totals) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    if (!c->initialised) return fail(c, LBM_ESTATE, "populations not initialised");
+    HIPCHK(c, hipSetDevice(c->device));
+    lbm_status st = dispatch<MomentsFn>(c, rho, u, p, totals);
+    if (st != LBM_OK) return st;
+    return poll_health(c, true);
+}

@@ -1,0 +1,367 @@
+// HIP kernels of the time step (gfx950). Population storage is SoA: plane i of the
+// buffer holds population i of every node (index n = x + nx (y + ny z)), planes `stride`
+// elements apart. The stored state is the post-collision f_bar* of the previous step; a
+// step pulls f_bar_i(x) = f_bar*_i(x - e_i) (Eq. (9) read backwards), or, when x - e_i is
+// solid, the halfway bounce-back value f_bar*_opp(i)(x).
+//
+// Two-pass step:
+//   k_density_psi  gather -> rho -> psi(rho); psi < 0 marks solid nodes
+//   k_collide      gather + psi of the 26-neighbourhood -> forces -> collision -> store
+#pragma once
+
+#include "lattice.h"
+
+namespace lbmk {
+
+template <typename T> struct Arith { using type = float; };
+template <> struct Arith<double> { using type = double; };
+
+template <typename T, typename R>
+__device__ __forceinline__ R load_as(const T* p) { return static_cast<R>(*p); }
+template <typename T, typename R>
+__device__ __forceinline__ void store_as(T* p, R v) { *p = static_cast<T>(v); }
+
+struct Grid {
+    int nx, ny, nz;
+    long long stride;         // elements between population planes
+};
+
+// Indices of x + e_j for all j (periodic wrap on every axis).
+template <int Q>
+__device__ __forceinline__ void neighbour_index(const Grid& g, int x, int y, int z, int* nb) {
+    const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+    const int nxy = g.nx * g.ny;
+    const int ox[3] = {xm, x, xp};
+    const int oy[3] = {ym * g.nx, y * g.nx, yp * g.nx};
+    const int oz[3] = {zm * nxy, z * nxy, zp * nxy};
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+        nb[j] = ox[vel_x(j) + 1] + oy[vel_y(j) + 1] + oz[vel_z(j) + 1];
+}
+
+// Pull the Q populations of node n, with bounce-back where the source is solid.
+template <int Q, typename T, typename R>
+__device__ __forceinline__ void gather(const T* __restrict__ f, long long stride, int n,
+                                       const int* nb, const bool* solid_nb, R* d) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int o = opposite(i);
+        // source x - e_i = x + e_o
+        const long long idx = solid_nb[o] ? (long long)o * stride + n
+                                          : (long long)i * stride + nb[o];
+        d[i] = load_as<T, R>(f + idx);
+    }
+}
+
+template <int Q, typename T, bool SOLID>
+__global__ __launch_bounds__(256) void k_density_psi(const T* __restrict__ f,
+                                                     const uint8_t* __restrict__ solid,
+                                                     typename Arith<T>::type* __restrict__ psi,
+                                                     Grid g, Phys<typename Arith<T>::type> P) {
+    using R = typename Arith<T>::type;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    const int n = x + g.nx * (y + g.ny * z);
+    if (SOLID && solid[n]) { psi[n] = R(-1); return; }
+    int nb[Q];
+    neighbour_index<Q>(g, x, y, z, nb);
+    bool snb[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) snb[j] = SOLID ? solid[nb[j]] != 0 : false;
+    R d[Q];
+    gather<Q, T, R>(f, g.stride, n, nb, snb, d);
+    R s = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) s += d[i];
+    psi[n] = pseudopotential<R>(P.rho_ref + s, P);
+}
+
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_collide(const T* __restrict__ fin, T* __restrict__ fout,
+                                                 const typename Arith<T>::type* __restrict__ psi,
+                                                 Grid g, Phys<typename Arith<T>::type> P) {
+    using R = typename Arith<T>::type;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    const int n = x + g.nx * (y + g.ny * z);
+    const R psi0 = psi[n];
+    if (psi0 < R(0)) return;                       // solid node: nothing stored
+    int nb[Q];
+    neighbour_index<Q>(g, x, y, z, nb);
+    R pn[Q];
+    bool snb[Q];
+#pragma unroll
+    for (int j = 1; j < Q; ++j) { pn[j] = psi[nb[j]]; snb[j] = pn[j] < R(0); }
+    pn[0] = psi0; snb[0] = false;
+    R d[Q];
+    gather<Q, T, R>(fin, g.stride, n, nb, snb, d);
+    const NodeForce<R> nf = node_force<Q, R>(psi0, pn, P);
+    collide<Q, R>(d, nf, P);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) store_as<T, R>(fout + (long long)i * g.stride + n, d[i]);
+}
+
+// Macroscopic fields at the current time: rho, u (with F/2), p = rho/3 + G psi^2/2, and
+// per-block partial sums of rho, rho u, rho |u|^2 / 2 for the totals.
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_moments(const T* __restrict__ fin,
+                                                 const typename Arith<T>::type* __restrict__ psi,
+                                                 double* __restrict__ rho_out,
+                                                 double* __restrict__ u_out,
+                                                 double* __restrict__ p_out,
+                                                 double* __restrict__ partial,
+                                                 Grid g, Phys<typename Arith<T>::type> P) {
+    using R = typename Arith<T>::type;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    double acc[5] = {0, 0, 0, 0, 0};
+    if (x < g.nx && y < g.ny) {
+        const int n = x + g.nx * (y + g.ny * z);
+        const R psi0 = psi[n];
+        if (psi0 < R(0)) {
+            rho_out[n] = 0; p_out[n] = 0;
+            u_out[n] = 0; u_out[N + n] = 0; u_out[2 * N + n] = 0;
+        } else {
+            int nb[Q];
+            neighbour_index<Q>(g, x, y, z, nb);
+            R pn[Q];
+            bool snb[Q];
+#pragma unroll
+            for (int j = 1; j < Q; ++j) { pn[j] = psi[nb[j]]; snb[j] = pn[j] < R(0); }
+            pn[0] = psi0; snb[0] = false;
+            R d[Q];
+            gather<Q, T, R>(fin, g.stride, n, nb, snb, d);
+            const NodeForce<R> nf = node_force<Q, R>(psi0, pn, P);
+            const Raw<R> k = forward<Q, R>(d);
+            const double rho = (double)P.rho_ref + (double)k.k000;
+            const double jx = (double)k.k100 + 0.5 * (double)nf.Fx;
+            const double jy = (double)k.k010 + 0.5 * (double)nf.Fy;
+            const double jz = (double)k.k001 + 0.5 * (double)nf.Fz;
+            const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
+            rho_out[n] = rho;
+            u_out[n] = ux; u_out[N + n] = uy; u_out[2 * N + n] = uz;
+            const double ps = (double)psi0;
+            p_out[n] = rho / 3.0 + 0.5 * (double)P.G * ps * ps;
+            acc[0] = rho; acc[1] = jx; acc[2] = jy; acc[3] = jz;
+            acc[4] = 0.5 * (jx * ux + jy * uy + jz * uz);
+        }
+    }
+    // block reduction: wavefront shuffles, then one value per wavefront through LDS
+    __shared__ double red[5][8];
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        double v = acc[c];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) red[c][wave] = v;
+    }
+    __syncthreads();
+    if (tid < 5) {
+        const int nw = (blockDim.x * blockDim.y + 63) / 64;
+        double s = 0;
+        for (int w = 0; w < nw; ++w) s += red[tid][w];
+        const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+        partial[b * 5 + tid] = s;
+    }
+}
+
+// Fixed-order sum of nblocks x 5 partials into out[5] (one block of 256 threads).
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial,
+                                                      long long nblocks, double* __restrict__ out) {
+    __shared__ double red[5][256];
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (long long b = threadIdx.x; b < nblocks; b += blockDim.x)
+        for (int c = 0; c < 5; ++c) acc[c] += partial[b * 5 + c];
+    for (int c = 0; c < 5; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int c = 0; c < 5; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Store f_bar(x) (float64, Q planes of N) into the pull layout: population i of node x
+// goes to the slot it will be pulled from, (x - e_i, i), or to (x, opp(i)) when x - e_i is
+// solid. Values are stored as deviations from w_i rho_ref.
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_scatter(const double* __restrict__ fsrc, T* __restrict__ f,
+                                                 const uint8_t* __restrict__ solid, Grid g,
+                                                 double rho_ref) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    const int n = x + g.nx * (y + g.ny * z);
+    if (solid[n]) return;
+    int nb[Q];
+    neighbour_index<Q>(g, x, y, z, nb);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int o = opposite(i);
+        const double v = fsrc[(long long)i * N + n] - omega<Q>(i) * rho_ref;
+        const long long idx = solid[nb[o]] ? (long long)o * g.stride + n
+                                           : (long long)i * g.stride + nb[o];
+        f[idx] = static_cast<T>(v);
+    }
+}
+
+// Read f_bar(x) back (float64, Q planes of N), 0 at solid nodes.
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_gather_out(const T* __restrict__ f, double* __restrict__ fdst,
+                                                    const uint8_t* __restrict__ solid, Grid g,
+                                                    double rho_ref) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    const int n = x + g.nx * (y + g.ny * z);
+    if (solid[n]) {
+        for (int i = 0; i < Q; ++i) fdst[(long long)i * N + n] = 0.0;
+        return;
+    }
+    int nb[Q];
+    neighbour_index<Q>(g, x, y, z, nb);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int o = opposite(i);
+        const long long idx = solid[nb[o]] ? (long long)o * g.stride + n
+                                           : (long long)i * g.stride + nb[o];
+        fdst[(long long)i * N + n] = static_cast<double>(f[idx]) + omega<Q>(i) * rho_ref;
+    }
+}
+
+// f_bar = M^-1 m^eq(rho, u) from float64 fields (u may be null), written in the pull
+// layout like k_scatter.
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_init_fields(const double* __restrict__ rho0,
+                                                     const double* __restrict__ u0,
+                                                     T* __restrict__ f,
+                                                     const uint8_t* __restrict__ solid, Grid g,
+                                                     Phys<typename Arith<T>::type> P) {
+    using R = typename Arith<T>::type;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    const int n = x + g.nx * (y + g.ny * z);
+    if (solid[n]) return;
+    R d[Q];
+    const R ux = u0 ? (R)u0[n] : R(0), uy = u0 ? (R)u0[N + n] : R(0), uz = u0 ? (R)u0[2 * N + n] : R(0);
+    equilibrium<Q, R>((R)rho0[n], ux, uy, uz, P.rho_ref, d);
+    int nb[Q];
+    neighbour_index<Q>(g, x, y, z, nb);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int o = opposite(i);
+        const long long idx = solid[nb[o]] ? (long long)o * g.stride + n
+                                           : (long long)i * g.stride + nb[o];
+        f[idx] = static_cast<T>(d[i]);
+    }
+}
+
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) used as a counter-based generator:
+// the value for counter n under seed s is the output for state s + (n+1) * golden gamma;
+// the uniform double in [0, 1) is the top 53 bits times 2^-53.
+__device__ __forceinline__ double splitmix_uniform(uint64_t seed, uint64_t n) {
+    uint64_t z = seed + (n + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Droplet initial density and velocity fields (float64), see lbm_init_droplet.
+__global__ __launch_bounds__(256) void k_droplet_fields(double* __restrict__ rho0, double* __restrict__ u0,
+                                                        Grid g, double cx, double cy, double cz,
+                                                        double R, double W, double rin, double rout,
+                                                        double ux, double uy, double uz,
+                                                        double amp, uint64_t seed) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
+    const double dx = x - cx, dy = y - cy, dz = z - cz;
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    double rho = 0.5 * (rin + rout) - 0.5 * (rin - rout) * tanh(2.0 * (r - R) / W);
+    double phi = (rho - rout) / (rin - rout);
+    phi = phi < 0.0 ? 0.0 : (phi > 1.0 ? 1.0 : phi);
+    if (amp != 0.0 && fabs(r - R) < W)
+        rho = rho * (1.0 + amp * (2.0 * splitmix_uniform(seed, (uint64_t)n) - 1.0));
+    rho0[n] = rho;
+    u0[n] = ux * phi; u0[N + n] = uy * phi; u0[2 * N + n] = uz * phi;
+}
+
+// Health check: per-block minimum of rho and a non-finite flag over fluid nodes, from the
+// psi pass's inputs (sum of populations). Writes partial[b] = (min rho, any non-finite).
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_health(const T* __restrict__ f,
+                                                const typename Arith<T>::type* __restrict__ psi,
+                                                double* __restrict__ partial, Grid g, double rho_ref) {
+    using R = typename Arith<T>::type;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    double mn = 1e300, bad = 0.0;
+    if (x < g.nx && y < g.ny) {
+        const int n = x + g.nx * (y + g.ny * z);
+        if (!(psi[n] < R(0))) {
+            double s = rho_ref;
+            for (int i = 0; i < Q; ++i) s += (double)f[(long long)i * g.stride + n];
+            if (!isfinite(s)) bad = 1.0; else mn = s;
+            if (!isfinite((double)psi[n])) bad = 1.0;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        mn = fmin(mn, __shfl_down(mn, off, 64));
+        bad = fmax(bad, __shfl_down(bad, off, 64));
+    }
+    __shared__ double red[2][8];
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    if ((tid & 63) == 0) { red[0][tid >> 6] = mn; red[1][tid >> 6] = bad; }
+    __syncthreads();
+    if (tid == 0) {
+        const int nw = (blockDim.x * blockDim.y + 63) / 64;
+        for (int w = 1; w < nw; ++w) { mn = fmin(mn, red[0][w]); bad = fmax(bad, red[1][w]); }
+        mn = fmin(mn, red[0][0]); bad = fmax(bad, red[1][0]);
+        const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+        partial[2 * b] = mn; partial[2 * b + 1] = bad;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_health_final(const double* __restrict__ partial,
+                                                      long long nblocks, double* __restrict__ out) {
+    __shared__ double red[2][256];
+    double mn = 1e300, bad = 0.0;
+    for (long long b = threadIdx.x; b < nblocks; b += blockDim.x) {
+        mn = fmin(mn, partial[2 * b]);
+        bad = fmax(bad, partial[2 * b + 1]);
+    }
+    red[0][threadIdx.x] = mn; red[1][threadIdx.x] = bad;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + s]);
+            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[0] = red[0][0]; out[1] = red[1][0]; }
+}
+
+}  // namespace lbmk

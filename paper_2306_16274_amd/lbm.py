@@ -1,0 +1,241 @@
+"""Python binding of the C ABI in include/lbm.h (argument marshalling only).
+
+Every function has the name of the C entry point it wraps and raises LbmError on a
+non-zero status. All lattice arithmetic runs in the HIP library; this module only moves
+numpy buffers in and out. torch is imported first so that the library shares torch's HIP
+runtime and can be given torch's current stream.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (provides the HIP runtime and the streams)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBRARY = os.path.join(HERE, "liblbm_hip.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+LBM_FP64, LBM_FP32, LBM_FP16 = 0, 1, 2
+LBM_EOS_CS, LBM_EOS_PIECEWISE = 0, 1
+LBM_BC_PERIODIC, LBM_BC_WALL = 0, 1
+
+STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
+                -4: "LBM_ENONFINITE", -5: "LBM_ESTATE"}
+
+
+class lbm_params(ctypes.Structure):
+    """Mirror of the C struct lbm_params (same field order and types)."""
+    _fields_ = [
+        ("lattice", ctypes.c_int32), ("storage", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("eos", ctypes.c_int32),
+        ("rho_ref", ctypes.c_double),
+        ("cs_a", ctypes.c_double), ("cs_b", ctypes.c_double), ("cs_R", ctypes.c_double),
+        ("T_over_Tc", ctypes.c_double),
+        ("pw_theta_v", ctypes.c_double), ("pw_theta_m", ctypes.c_double),
+        ("pw_theta_l", ctypes.c_double), ("pw_rho1", ctypes.c_double), ("pw_rho2", ctypes.c_double),
+        ("G", ctypes.c_double), ("sigma", ctypes.c_double), ("kappa", ctypes.c_double),
+        ("G_ads", ctypes.c_double),
+        ("nu_l", ctypes.c_double), ("nu_v", ctypes.c_double),
+        ("rho_l", ctypes.c_double), ("rho_v", ctypes.c_double),
+        ("s0", ctypes.c_double), ("s1", ctypes.c_double), ("s2b", ctypes.c_double),
+        ("s3", ctypes.c_double), ("s3b", ctypes.c_double), ("s4", ctypes.c_double),
+        ("s4b", ctypes.c_double), ("s5", ctypes.c_double), ("s6", ctypes.c_double),
+        ("bc", (ctypes.c_int32 * 2) * 3),
+        ("cylinder", ctypes.c_int32),
+        ("cyl_y", ctypes.c_double), ("cyl_z", ctypes.c_double), ("cyl_r", ctypes.c_double),
+        ("body_force", ctypes.c_double * 3),
+        ("stream", ctypes.c_void_p),
+        ("reduce_every", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+_D = ctypes.c_double
+_P = ctypes.c_void_p
+_SIGS = {
+    "lbm_params_default": (ctypes.c_int, [ctypes.POINTER(lbm_params)]),
+    "lbm_create": (ctypes.c_int, [ctypes.POINTER(lbm_params), ctypes.POINTER(_P)]),
+    "lbm_destroy": (ctypes.c_int, [_P]),
+    "lbm_last_error": (ctypes.c_char_p, [_P]),
+    "lbm_init_droplet": (ctypes.c_int, [_P, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D,
+                                        ctypes.c_uint64]),
+    "lbm_init_fields": (ctypes.c_int, [_P, _P, _P]),
+    "lbm_set_populations": (ctypes.c_int, [_P, _P]),
+    "lbm_get_populations": (ctypes.c_int, [_P, _P]),
+    "lbm_step": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "lbm_steps_done": (ctypes.c_int64, [_P]),
+    "lbm_moments": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "lbm_synchronize": (ctypes.c_int, [_P]),
+    "lbm_coexistence": (ctypes.c_int, [ctypes.POINTER(lbm_params), ctypes.POINTER(_D),
+                                       ctypes.POINTER(_D)]),
+    "lbm_footprint_bytes": (ctypes.c_int64, [ctypes.POINTER(lbm_params)]),
+}
+
+
+def library():
+    """Load liblbm_hip.so (built in-tree by build.build()); fail loudly if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBRARY):
+            raise ImportError(f"{LIBRARY} is missing: build it with "
+                              "paper_2306_16274_amd.build.build()")
+        lib = ctypes.CDLL(LIBRARY)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status, ctx=None):
+    if status != LBM_OK:
+        msg = library().lbm_last_error(ctx)
+        raise LbmError(status, msg.decode() if msg else "")
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def lbm_params_default():
+    p = lbm_params()
+    _check(library().lbm_params_default(ctypes.byref(p)))
+    return p
+
+
+def lbm_create(params):
+    ctx = ctypes.c_void_p()
+    _check(library().lbm_create(ctypes.byref(params), ctypes.byref(ctx)))
+    return ctx
+
+
+def lbm_destroy(ctx):
+    _check(library().lbm_destroy(ctx))
+
+
+def lbm_last_error(ctx=None):
+    msg = library().lbm_last_error(ctx)
+    return msg.decode() if msg else ""
+
+
+def lbm_init_droplet(ctx, cx, cy, cz, R, W, rho_in, rho_out, ux=0.0, uy=0.0, uz=0.0,
+                     noise_amp=0.0, seed=0):
+    _check(library().lbm_init_droplet(ctx, cx, cy, cz, R, W, rho_in, rho_out, ux, uy, uz,
+                                      noise_amp, seed), ctx)
+
+
+def lbm_init_fields(ctx, rho, u=None):
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    uu = None if u is None else np.ascontiguousarray(u, dtype=np.float64)
+    _check(library().lbm_init_fields(ctx, _ptr(rho), None if uu is None else _ptr(uu)), ctx)
+
+
+def lbm_set_populations(ctx, f):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    _check(library().lbm_set_populations(ctx, _ptr(f)), ctx)
+
+
+def lbm_get_populations(ctx, Q, shape):
+    """Returns f_bar(x, t) as an array (Q, nz, ny, nx)."""
+    out = np.empty((Q,) + tuple(shape), dtype=np.float64)
+    _check(library().lbm_get_populations(ctx, _ptr(out)), ctx)
+    return out
+
+
+def lbm_step(ctx, nsteps):
+    _check(library().lbm_step(ctx, int(nsteps)), ctx)
+
+
+def lbm_steps_done(ctx):
+    return library().lbm_steps_done(ctx)
+
+
+def lbm_moments(ctx, shape, want=("rho", "u", "p", "totals")):
+    """Returns dict with rho (nz,ny,nx), u (3,nz,ny,nx), p, totals (5,) as requested."""
+    out = {}
+    rho = np.empty(shape) if "rho" in want else None
+    u = np.empty((3,) + tuple(shape)) if "u" in want else None
+    p = np.empty(shape) if "p" in want else None
+    tot = np.empty(5) if "totals" in want else None
+    _check(library().lbm_moments(ctx, None if rho is None else _ptr(rho),
+                                 None if u is None else _ptr(u),
+                                 None if p is None else _ptr(p),
+                                 None if tot is None else _ptr(tot)), ctx)
+    for k, v in (("rho", rho), ("u", u), ("p", p), ("totals", tot)):
+        if v is not None:
+            out[k] = v
+    return out
+
+
+def lbm_synchronize(ctx):
+    _check(library().lbm_synchronize(ctx), ctx)
+
+
+def lbm_coexistence(params):
+    rv, rl = ctypes.c_double(), ctypes.c_double()
+    _check(library().lbm_coexistence(ctypes.byref(params), ctypes.byref(rv), ctypes.byref(rl)))
+    return rv.value, rl.value
+
+
+def lbm_footprint_bytes(params):
+    return library().lbm_footprint_bytes(ctypes.byref(params))
+
+
+class Lattice:
+    """Owns one context; a convenience wrapper over the functions above."""
+
+    def __init__(self, params, use_torch_stream=True):
+        if use_torch_stream and params.stream is None and torch.cuda.is_available():
+            params.stream = torch.cuda.current_stream().cuda_stream
+        self.params = params
+        self.Q = params.lattice
+        self.shape = (params.nz, params.ny, params.nx)
+        self.ctx = lbm_create(params)
+
+    def close(self):
+        if self.ctx is not None:
+            lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_droplet(self, *a, **k):
+        lbm_init_droplet(self.ctx, *a, **k)
+
+    def init_fields(self, rho, u=None):
+        lbm_init_fields(self.ctx, rho, u)
+
+    def set_populations(self, f):
+        lbm_set_populations(self.ctx, f)
+
+    def get_populations(self):
+        return lbm_get_populations(self.ctx, self.Q, self.shape)
+
+    def step(self, n=1):
+        lbm_step(self.ctx, n)
+
+    def moments(self, want=("rho", "u", "p", "totals")):
+        return lbm_moments(self.ctx, self.shape, want)
+
+    def synchronize(self):
+        lbm_synchronize(self.ctx)
