@@ -1,0 +1,231 @@
+"""Throughput benchmark of the fused lattice update on one MI355X.
+
+One step is one time step of the whole hot path (streaming with bounce-back, density and
+pseudopotential, interaction / wetting / surface-tension terms, moment-space collision,
+back-transform, store) over the lattice of the workload. The workload is a 256^3 D3Q19
+static droplet (Carnahan-Starling EOS at T = 0.5 T_c, paper relaxation rates, +-1 %
+interface noise), populations resident in HBM before timing starts.
+
+Prints one JSON line (rank 0): the FP32 shifted-storage throughput in MLUPS as `value`,
+the FP64 throughput beside it, the HBM roofline of the dominant kernel measured with HIP
+events on the launch stream, and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak, GB/s
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("lattice.h", "kernels.h", "api.hip"):
+        with open(os.path.join(ROOT, "paper_2306_16274_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, storage):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or
+    None if the summary is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    if data.get("source_hash") != kernel_source_hash():
+        return None
+    entry = data.get("kernels", {}).get(f"{kernel}|{workload}|{storage}")
+    return None if entry is None else entry.get("bytes_per_launch")
+
+
+def make_params(w, storage, rho_ref, rho_v, rho_l, step_kernel="fused"):
+    from paper_2306_16274_amd import lbm as L
+    p = L.lbm_params_default()
+    p.lattice = w.Q
+    p.storage = {"fp64": L.LBM_FP64, "fp32": L.LBM_FP32, "fp16": L.LBM_FP16}[storage]
+    p.nx, p.ny, p.nz = w.nx, w.ny, w.nz
+    p.rho_ref = rho_ref
+    p.eos = L.LBM_EOS_CS
+    p.cs_a, p.cs_b, p.cs_R, p.T_over_Tc = w.cs_a, w.cs_b, w.cs_R, w.T_over_Tc
+    p.G, p.sigma, p.kappa, p.G_ads = w.G, w.sigma, w.kappa, w.G_ads
+    p.nu_l = p.nu_v = w.nu
+    if w.rates == "unit":
+        for k in ("s2b", "s3", "s3b", "s4", "s4b", "s5", "s6"):
+            setattr(p, k, 1.0)
+    p.reduce_every = 0
+    p.step_kernel = L.LBM_STEP_FUSED if step_kernel == "fused" else L.LBM_STEP_TWO_PASS
+    return p
+
+
+def run_gpu(w, storage, steps, warmup, rho_ref_choice="vapour", step_kernel="fused"):
+    import torch
+    from paper_2306_16274_amd import lbm as L
+    p0 = make_params(w, storage, 0.0, 0.0, 0.0)
+    rho_v, rho_l = L.lbm_coexistence(p0)
+    rho_ref = 0.0 if storage == "fp64" else {"zero": 0.0, "vapour": rho_v, "liquid": rho_l}[rho_ref_choice]
+    p = make_params(w, storage, rho_ref, rho_v, rho_l, step_kernel)
+    # a dedicated (default-priority) stream: the library launches on it and the timing
+    # events are recorded on it
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    p.stream = stream.cuda_stream
+    assert p.stream, "expected a non-null HIP stream handle"
+    lat = L.Lattice(p)
+    cx, cy, cz = w.droplet_centre()
+    lat.init_droplet(cx, cy, cz, w.R, w.W, rho_l, rho_v, 0.0, 0.0, 0.0, w.noise, w.seed)
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    lat.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    ktimes = lat.kernel_times(max(3, min(steps, 20)))
+    mom = lat.moments(want=("totals",))
+    lat.close()
+    torch.cuda.set_stream(torch.cuda.default_stream())
+    return dict(ms=ms, ms_per_step=ms / steps, mlups=w.nodes * steps / (ms * 1e-3) / 1e6,
+                kernel_ms=ktimes, rho_ref=rho_ref, rho_v=rho_v, rho_l=rho_l,
+                mass=float(mom["totals"][0]))
+
+
+def copy_bandwidth(nbytes=2 << 30, reps=10):
+    """Attainable HBM bandwidth of a plain device copy (read + write bytes / time)."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    t1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (t0.elapsed_time(t1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The FP64 CPU oracle on a bounded sample of the workload: a 64^3 box with the same
+    physics (droplet radius scaled by 1/4), single thread."""
+    from threadpoolctl import threadpool_limits
+    import synth_inputs as si
+    from oracle import lbm as olbm
+    from tests.helpers import maxwell, oracle_params
+    n = 64
+    ws = w.with_(nx=n, ny=n, nz=n, R=w.R / 4.0)
+    with threadpool_limits(limits=1):
+        rv, rl = maxwell(ws)
+        P = oracle_params(ws)
+        cx, cy, cz = ws.droplet_centre()
+        rho, u = olbm.droplet_fields(P, cx, cy, cz, ws.R, ws.W, rl, rv, noise_amp=ws.noise,
+                                     seed=ws.seed)
+        f = olbm.equilibrium_populations(P, rho, u)
+        solid = olbm.solid_mask(P)
+        f = olbm.step(f, P, solid)          # warm-up
+        steps, t = 0, 0.0
+        t0 = time.perf_counter()
+        while t < budget_s:
+            f = olbm.step(f, P, solid)
+            steps += 1
+            t = time.perf_counter() - t0
+    return dict(value=ws.nodes * steps / t / 1e6, unit="MLUPS", cores=1, kind="oracle",
+                sample=f"{n}^3 D3Q19 box of the same workload (droplet R={ws.R:g}), "
+                       f"{steps} FP64 numpy steps in {t:.1f} s, one thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--fp64-steps", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rho-ref", default="vapour", choices=["zero", "vapour", "liquid"])
+    ap.add_argument("--step-kernel", default="fused", choices=["fused", "two_pass"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the lattice update "
+              "is benchmarked on a single MI355X; multi-GPU runs are not part of this build.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth_inputs as si
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w = si.LAPLACE_256
+    Q = w.Q
+
+    r32 = run_gpu(w, "fp32", args.steps, args.warmup, args.rho_ref, args.step_kernel)
+    r64 = run_gpu(w, "fp64", args.fp64_steps, max(2, args.warmup // 4), "zero", args.step_kernel)
+    copy_gbs = copy_bandwidth()
+
+    # dominant kernel of the FP32 step and its algorithmic bytes per node
+    kname, kms = max(r32["kernel_ms"].items(), key=lambda kv: kv[1])
+    b = 4
+    per_node = {"k_step_fused": 2 * Q * b,           # populations in + out
+                "k_collide": 2 * Q * b + 4,          # populations in + out, psi of the node
+                "k_density_psi": Q * b + 4}[kname]    # populations in, psi out
+    alg_bytes = per_node * w.nodes
+    achieved = alg_bytes / (kms * 1e-3) / 1e9
+    traffic = measured_traffic(kname, w.name, "fp32")
+    step_bytes = 2 * Q * b * w.nodes                  # method minimum per step
+    effective = step_bytes / (r32["ms_per_step"] * 1e-3) / 1e9
+    eff64 = 2 * Q * 8 * w.nodes / (r64["ms_per_step"] * 1e-3) / 1e9
+
+    out = {
+        "metric": "MLUPS, D3Q19 multiphase 256^3, FP32 shifted storage (FP64 beside it)",
+        "value": round(r32["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "lattice": "D3Q19", "nodes": w.nodes,
+                   "step_kernel": args.step_kernel,
+                   "eos": "carnahan-starling", "T_over_Tc": w.T_over_Tc,
+                   "storage": "fp32 shifted", "rho_ref": r32["rho_ref"],
+                   "droplet_R": w.R, "noise": w.noise},
+        "fp64": {"value": round(r64["mlups"], 1), "unit": "MLUPS",
+                 "ms_per_step": round(r64["ms_per_step"], 4), "steps": args.fp64_steps,
+                 "effective_GBs": round(eff64, 1),
+                 "effective_frac": round(eff64 / HBM_PEAK_GBS, 4),
+                 "kernel_ms": r64["kernel_ms"]},
+        "effective_step_GBs": round(effective, 1),
+        "effective_step_frac": round(effective / HBM_PEAK_GBS, 4),
+        "kernel_ms": r32["kernel_ms"],
+        "copy_kernel_GBs": round(copy_gbs, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": kname,
+                     "alg_bytes_per_node": per_node},
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(w),
+        "mass": r32["mass"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

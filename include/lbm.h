@@ -48,6 +48,7 @@ typedef enum {
 enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16 = 2 };       /* population storage type   */
 enum { LBM_EOS_CS = 0, LBM_EOS_PIECEWISE = 1 };          /* equation of state         */
 enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1 };           /* per domain face           */
+enum { LBM_STEP_FUSED = 0, LBM_STEP_TWO_PASS = 1 };      /* kernel schedule of a step */
 
 /*
  * Problem statement. Defaults (lbm_params_default) follow Sec. II B: s0 = s1 = 1,
@@ -83,7 +84,10 @@ typedef struct {
     double body_force[3];     /* uniform body force added to F (default 0)               */
     void* stream;             /* hipStream_t to enqueue on, or NULL                      */
     int32_t reduce_every;     /* health check cadence in steps (0 = never)               */
-    int32_t reserved;
+    int32_t step_kernel;      /* LBM_STEP_FUSED: one pass per step, rho/psi of a tile halo
+                                 recomputed on chip (default). LBM_STEP_TWO_PASS: a
+                                 density/psi pass, then the collision pass. Same results
+                                 up to rounding order.                                    */
 } lbm_params;
 
 /* Fill *p with the defaults above (D3Q19, FP32, 64^3, CS EOS at T = 0.7 T_c, a = 0.5,
@@ -138,6 +142,13 @@ int64_t lbm_steps_done(const lbm_ctx* c);
    sums over fluid nodes of rho, rho u_x, rho u_y, rho u_z and rho |u|^2 / 2. Solid nodes
    read 0. Synchronous.                                                                 */
 lbm_status lbm_moments(lbm_ctx* c, double* rho, double* u, double* p, double* totals);
+
+/* Measurement aid: run nsteps time steps (as lbm_step) with a HIP event pair around every
+   kernel launch on the context stream, waiting after each step. avg_ms[k] receives the
+   mean duration in ms of the k-th kernel of a step and names[k] (if names != NULL) its
+   name (static strings); *count the number of kernels per step (at most cap).          */
+lbm_status lbm_kernel_times(lbm_ctx* c, int64_t nsteps, double* avg_ms, const char** names,
+                            int32_t cap, int32_t* count);
 
 /* Wait for all work enqueued on the context stream.                                   */
 lbm_status lbm_synchronize(lbm_ctx* c);

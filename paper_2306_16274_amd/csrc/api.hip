@@ -13,7 +13,7 @@
 #include <vector>
 
 #include "../../include/lbm.h"
-#include "kernels.h"
+#include "fused.h"
 
 using namespace lbmk;
 
@@ -234,6 +234,8 @@ static lbm_status validate(const lbm_params& p) {
             if (p.bc[a][s] != LBM_BC_PERIODIC && p.bc[a][s] != LBM_BC_WALL)
                 return fail(nullptr, LBM_EINVAL, "unknown boundary condition");
     if (p.reduce_every < 0) return fail(nullptr, LBM_EINVAL, "reduce_every must be >= 0");
+    if (p.step_kernel != LBM_STEP_FUSED && p.step_kernel != LBM_STEP_TWO_PASS)
+        return fail(nullptr, LBM_EINVAL, "unknown step_kernel");
     return LBM_OK;
 }
 
@@ -397,12 +399,66 @@ static lbm_status dispatch(lbm_ctx* c, A... args) {
     return Fn<27, _Float16>::run(c, args...);
 }
 
+// Optional per-kernel timing of a step: an event pair around each launch.
+struct KernelTimer {
+    static constexpr int kMax = 4;
+    hipEvent_t ev[2 * kMax];
+    double total_ms[kMax];
+    int nk = 0;
+};
+static const char* const kTwoPassNames[] = {"k_density_psi", "k_collide"};
+static const char* const kFusedNames[] = {"k_step_fused"};
+
+constexpr int kTileX = 32, kTileY = 8;
+
+template <int Q, typename T>
+static void launch_fused(lbm_ctx* c, const void* fin, void* fout) {
+    using R = typename Arith<T>::type;
+    const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
+                                                         ? (const void*)&c->pd : (const void*)&c->pf);
+    const int ntx = (c->p.nx + kTileX - 1) / kTileX, nty = (c->p.ny + kTileY - 1) / kTileY;
+    // about 4096 workgroups (16 per CU), chunks of at least 4 planes
+    const long long tiles = (long long)ntx * nty;
+    long long nch = (4096 + tiles - 1) / tiles;
+    int zc = (int)((c->p.nz + nch - 1) / nch);
+    if (zc < 4) zc = std::min(4, c->p.nz);
+    const int nchunks = (c->p.nz + zc - 1) / zc;
+    const dim3 grid((unsigned)(tiles * nchunks)), block(kTileX * kTileY);
+    if (c->any_solid)
+        hipLaunchKernelGGL((k_step_fused<Q, T, true, kTileX, kTileY>), grid, block, 0, c->stream,
+                           (const T*)fin, (T*)fout, c->solid, grid_of(c), P, ntx, nty, zc);
+    else
+        hipLaunchKernelGGL((k_step_fused<Q, T, false, kTileX, kTileY>), grid, block, 0, c->stream,
+                           (const T*)fin, (T*)fout, c->solid, grid_of(c), P, ntx, nty, zc);
+}
+
 template <int Q, typename T>
 struct StepFn {
-    static lbm_status run(lbm_ctx* c, int64_t nsteps) {
+    static lbm_status run(lbm_ctx* c, int64_t nsteps, KernelTimer* tm = nullptr) {
+        const bool fused = c->p.step_kernel == LBM_STEP_FUSED;
         for (int64_t s = 0; s < nsteps; ++s) {
-            launch_psi<Q, T>(c, c->f[c->cur]);
-            launch_collide<Q, T>(c, c->f[c->cur], c->f[1 - c->cur]);
+            if (fused) {
+                if (tm) HIPCHK(c, hipEventRecord(tm->ev[0], c->stream));
+                launch_fused<Q, T>(c, c->f[c->cur], c->f[1 - c->cur]);
+                if (tm) HIPCHK(c, hipEventRecord(tm->ev[1], c->stream));
+                if (tm) tm->nk = 1;
+            } else {
+                if (tm) HIPCHK(c, hipEventRecord(tm->ev[0], c->stream));
+                launch_psi<Q, T>(c, c->f[c->cur]);
+                if (tm) HIPCHK(c, hipEventRecord(tm->ev[1], c->stream));
+                if (tm) HIPCHK(c, hipEventRecord(tm->ev[2], c->stream));
+                launch_collide<Q, T>(c, c->f[c->cur], c->f[1 - c->cur]);
+                if (tm) HIPCHK(c, hipEventRecord(tm->ev[3], c->stream));
+                if (tm) tm->nk = 2;
+            }
+            if (tm) {
+                HIPCHK(c, hipEventSynchronize(tm->ev[2 * tm->nk - 1]));
+                for (int k = 0; k < tm->nk; ++k) {
+                    float ms = 0.f;
+                    HIPCHK(c, hipEventElapsedTime(&ms, tm->ev[2 * k], tm->ev[2 * k + 1]));
+                    tm->total_ms[k] += ms;
+                }
+            }
             c->cur = 1 - c->cur;
             c->steps++;
             if (c->p.reduce_every > 0 && c->steps % c->p.reduce_every == 0) {
@@ -448,7 +504,28 @@ extern "C" lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
     HIPCHK(c, hipSetDevice(c->device));
     lbm_status st = poll_health(c, false);
     if (st != LBM_OK) return st;
-    return dispatch<StepFn>(c, nsteps);
+    return dispatch<StepFn>(c, nsteps, (KernelTimer*)nullptr);
+}
+
+extern "C" lbm_status lbm_kernel_times(lbm_ctx* c, int64_t nsteps, double* avg_ms,
+                                       const char** names, int32_t cap, int32_t* count) {
+    if (!c || !avg_ms || !count || cap < 1) return fail(c, LBM_EINVAL, "null argument");
+    if (nsteps < 1) return fail(c, LBM_EINVAL, "nsteps must be >= 1");
+    if (!c->initialised) return fail(c, LBM_ESTATE, "populations not initialised");
+    if (c->failed) return fail(c, LBM_ESTATE, "a previous health check failed");
+    HIPCHK(c, hipSetDevice(c->device));
+    KernelTimer tm{};
+    for (int k = 0; k < 2 * KernelTimer::kMax; ++k) HIPCHK(c, hipEventCreate(&tm.ev[k]));
+    lbm_status st = dispatch<StepFn>(c, nsteps, &tm);
+    for (int k = 0; k < 2 * KernelTimer::kMax; ++k) hipEventDestroy(tm.ev[k]);
+    if (st != LBM_OK) return st;
+    const int n = std::min<int>(tm.nk, cap);
+    for (int k = 0; k < n; ++k) {
+        avg_ms[k] = tm.total_ms[k] / (double)nsteps;
+        if (names) names[k] = c->p.step_kernel == LBM_STEP_FUSED ? kFusedNames[k] : kTwoPassNames[k];
+    }
+    *count = n;
+    return LBM_OK;
 }
 
 extern "C" lbm_status lbm_synchronize(lbm_ctx* c) {

@@ -18,6 +18,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1,
 LBM_FP64, LBM_FP32, LBM_FP16 = 0, 1, 2
 LBM_EOS_CS, LBM_EOS_PIECEWISE = 0, 1
 LBM_BC_PERIODIC, LBM_BC_WALL = 0, 1
+LBM_STEP_FUSED, LBM_STEP_TWO_PASS = 0, 1
 
 STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
                 -4: "LBM_ENONFINITE", -5: "LBM_ESTATE"}
@@ -47,7 +48,7 @@ class lbm_params(ctypes.Structure):
         ("body_force", ctypes.c_double * 3),
         ("stream", ctypes.c_void_p),
         ("reduce_every", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("step_kernel", ctypes.c_int32),
     ]
 
 
@@ -75,6 +76,7 @@ _SIGS = {
     "lbm_steps_done": (ctypes.c_int64, [_P]),
     "lbm_moments": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "lbm_synchronize": (ctypes.c_int, [_P]),
+    "lbm_kernel_times": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, ctypes.c_int32, _P]),
     "lbm_coexistence": (ctypes.c_int, [ctypes.POINTER(lbm_params), ctypes.POINTER(_D),
                                        ctypes.POINTER(_D)]),
     "lbm_footprint_bytes": (ctypes.c_int64, [ctypes.POINTER(lbm_params)]),
@@ -177,6 +179,16 @@ def lbm_moments(ctx, shape, want=("rho", "u", "p", "totals")):
     return out
 
 
+def lbm_kernel_times(ctx, nsteps, cap=8):
+    """Returns {kernel name: mean duration in ms} over nsteps timed steps."""
+    avg = (ctypes.c_double * cap)()
+    names = (ctypes.c_char_p * cap)()
+    count = ctypes.c_int32()
+    _check(library().lbm_kernel_times(ctx, int(nsteps), ctypes.cast(avg, _P),
+                                      ctypes.cast(names, _P), cap, ctypes.byref(count)), ctx)
+    return {names[k].decode(): avg[k] for k in range(count.value)}
+
+
 def lbm_synchronize(ctx):
     _check(library().lbm_synchronize(ctx), ctx)
 
@@ -239,3 +251,6 @@ class Lattice:
 
     def synchronize(self):
         lbm_synchronize(self.ctx)
+
+    def kernel_times(self, nsteps):
+        return lbm_kernel_times(self.ctx, nsteps)

@@ -71,20 +71,34 @@ def test_init_droplet_matches_oracle(L, Q):
     assert abs_err(g, fo) < 1e-15
 
 
+KERNELS = pytest.mark.parametrize("kernel", ["fused", "two_pass"])
+
+
+def kernel_code(L, kernel):
+    return L.LBM_STEP_FUSED if kernel == "fused" else L.LBM_STEP_TWO_PASS
+
+
+@KERNELS
 @pytest.mark.parametrize("Q", [19, 27])
-@pytest.mark.parametrize("geometry", ["periodic", "walls"])
-def test_fp64_brute_force_tiny_box(L, Q, geometry):
+@pytest.mark.parametrize("geometry", ["periodic", "walls", "ragged"])
+def test_fp64_brute_force_tiny_box(L, Q, geometry, kernel):
     """8^3 boxes (ragged 9x8x7 for walls) with every term switched on: sigma, kappa,
     wetting, a cylinder, density-dependent viscosity; 1 and 20 steps."""
     if geometry == "periodic":
         w = si.Workload("tiny", Q, 8, 8, 8, sigma=0.1, kappa=0.4, nu=0.05, T_over_Tc=0.6)
         over = {}
         gover = {}
-    else:
+    elif geometry == "walls":
         w = si.Workload("tiny", Q, 9, 8, 7, sigma=0.12, kappa=0.3, G_ads=0.15, nu=0.05,
                         T_over_Tc=0.6, walls=("z_lo", "z_hi"), cylinder=(4.0, 3.0, 1.2))
         over = dict(nu_v=0.15, rho_l=0.4, rho_v=0.01)
         gover = dict(nu_v=0.15, rho_l=0.4, rho_v=0.01)
+    else:
+        # several tiles in x and y with ragged tails, chunked z, a wall on one face only
+        w = si.Workload("ragged", Q, 37, 19, 11, sigma=0.1, kappa=0.2, G_ads=-0.1, nu=0.08,
+                        T_over_Tc=0.6, walls=("y_lo",))
+        over, gover = {}, {}
+    gover = dict(gover, step_kernel=kernel_code(L, kernel))
     rho, u = si.random_fields(w.shape, seed=3, rho_lo=0.05, rho_hi=0.4)
     P, solid, f0 = oracle_state_from_fields(w, rho, u, **over)
     f0 = f0 * si.random_factors(Q, w.shape, seed=3, amp=0.02)
@@ -115,9 +129,10 @@ def static32_oracle():
     return w, P, f0, f100, dens
 
 
-def test_fp64_static_droplet_100_steps(L, static32_oracle):
+@KERNELS
+def test_fp64_static_droplet_100_steps(L, static32_oracle, kernel):
     w, P, f0, f100, (rv, rl) = static32_oracle
-    with L.Lattice(gpu_params(w, "fp64")) as lat:
+    with L.Lattice(gpu_params(w, "fp64", step_kernel=kernel_code(L, kernel))) as lat:
         cx, cy, cz = w.droplet_centre()
         lat.init_droplet(cx, cy, cz, w.R, w.W, rl, rv)
         lat.step(100)
@@ -132,11 +147,13 @@ def test_fp64_static_droplet_100_steps(L, static32_oracle):
     assert abs(mom["totals"][0] - tot[0]) / tot[0] < 1e-13
 
 
+@KERNELS
 @pytest.mark.parametrize("rho_ref_kind", ["zero", "vapour"])
-def test_fp32_shifted_static_droplet_100_steps(L, static32_oracle, rho_ref_kind):
+def test_fp32_shifted_static_droplet_100_steps(L, static32_oracle, rho_ref_kind, kernel):
     w, P, f0, f100, (rv, rl) = static32_oracle
     rho_ref = 0.0 if rho_ref_kind == "zero" else rv
-    with L.Lattice(gpu_params(w, "fp32", rho_ref=rho_ref)) as lat:
+    with L.Lattice(gpu_params(w, "fp32", rho_ref=rho_ref,
+                              step_kernel=kernel_code(L, kernel))) as lat:
         cx, cy, cz = w.droplet_centre()
         lat.init_droplet(cx, cy, cz, w.R, w.W, rl, rv)
         lat.step(100)
@@ -191,3 +208,50 @@ def test_health_check_reports_non_finite(L):
         with pytest.raises(L.LbmError) as ei:
             lat.step(1)
         assert ei.value.status == L.LBM_ESTATE
+
+
+def _window(f, z, y, x, h):
+    """Periodic sub-box of f (Q, nz, ny, nx) of half-width h around (z, y, x)."""
+    Q, nz, ny, nx = f.shape
+    iz = np.arange(z - h, z + h + 1) % nz
+    iy = np.arange(y - h, y + h + 1) % ny
+    ix = np.arange(x - h, x + h + 1) % nx
+    return f[:, iz][:, :, iy][:, :, :, ix]
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_full_size_256_sampled_windows(L, storage):
+    """The benchmark workload at full size (256^3 D3Q19, CS at 0.5 T_c, paper rates,
+    +-1 % interface noise) in the benchmark's launch configuration: after 3 GPU steps the
+    state is read back, one more GPU step is taken, and the oracle advances 12 sampled
+    windows of 13^3 nodes by one step from the read-back state; the inner 9^3 of each
+    window (unaffected by the window edge) must match."""
+    w = si.LAPLACE_256
+    rv, rl = maxwell(w)
+    rho_ref = rv if storage == "fp32" else 0.0
+    P = oracle_params(w)
+    cx, cy, cz = w.droplet_centre()
+    with L.Lattice(gpu_params(w, storage, rho_ref=rho_ref)) as lat:
+        lat.init_droplet(cx, cy, cz, w.R, w.W, rl, rv, 0.0, 0.0, 0.0, w.noise, w.seed)
+        lat.step(3)
+        f3 = lat.get_populations()
+        lat.step(1)
+        f4 = lat.get_populations()
+    rng = np.random.default_rng(256)
+    # windows on the interface, inside the droplet, in the vapour and across the wrap
+    centres = [(cz, cy, cx + w.R), (cz + w.R, cy, cx), (cz, cy, cx), (0, 0, 0),
+               (255, 128, 3), (cz, cy - w.R, cx)]
+    centres += [tuple(int(v) for v in rng.integers(0, 256, 3)) for _ in range(6)]
+    h, inner = 6, slice(2, -2)
+    Pw = oracle_params(w.with_(nx=2 * h + 1, ny=2 * h + 1, nz=2 * h + 1))
+    worst = 0.0
+    for (z, y, x) in centres:
+        z, y, x = int(z), int(y), int(x)
+        fo = olbm.step(_window(f3, z, y, x, h), Pw)[:, inner, inner, inner]
+        fg = _window(f4, z, y, x, h)[:, inner, inner, inner]
+        rho_o, rho_g = fo.sum(0), fg.sum(0)
+        worst = max(worst, float(np.max(np.abs(rho_g - rho_o) / rho_o)))
+        if storage == "fp64":
+            assert rel_err(fg, fo) < 1e-12, (z, y, x)
+    print(f"256^3 {storage}: worst sampled relative rho error after one step {worst:.2e}")
+    assert worst < (1e-12 if storage == "fp64" else 1e-6)
