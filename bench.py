@@ -25,24 +25,29 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak, GB/s
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("lattice.h", "kernels.h", "api.hip"):
+    for name in ("lattice.h", "kernels.h", "fused.h", "api.hip"):
         with open(os.path.join(ROOT, "paper_2306_16274_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload, storage):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or
-    None if the summary is missing or was taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+def measured_traffic(kernel, storage):
+    """HBM bytes per launch of `kernel` on the benchmark workload, from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
+    reads for a plain copy of known size), or None when the summary is missing or was
+    taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{kernel}_{storage}_d3q19_256cube.txt")
     if not os.path.exists(path):
         return None
+    vals = {}
     with open(path) as fh:
-        data = json.load(fh)
-    if data.get("source_hash") != kernel_source_hash():
+        for line in fh:
+            parts = line.split()
+            if len(parts) == 2 and not line.startswith("#"):
+                vals[parts[0]] = parts[1]
+    if vals.get("source_hash") != kernel_source_hash():
         return None
-    entry = data.get("kernels", {}).get(f"{kernel}|{workload}|{storage}")
-    return None if entry is None else entry.get("bytes_per_launch")
+    return float(vals["hbm_bytes_per_launch"])
 
 
 def make_params(w, storage, rho_ref, rho_v, rho_l, step_kernel="fused"):
@@ -185,7 +190,7 @@ def main():
                 "k_density_psi": Q * b + 4}[kname]    # populations in, psi out
     alg_bytes = per_node * w.nodes
     achieved = alg_bytes / (kms * 1e-3) / 1e9
-    traffic = measured_traffic(kname, w.name, "fp32")
+    traffic = measured_traffic(kname, "fp32")
     step_bytes = 2 * Q * b * w.nodes                  # method minimum per step
     effective = step_bytes / (r32["ms_per_step"] * 1e-3) / 1e9
     eff64 = 2 * Q * 8 * w.nodes / (r64["ms_per_step"] * 1e-3) / 1e9
@@ -220,10 +225,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": kname,
-                     "alg_bytes_per_node": per_node},
+                     "alg_bytes_per_node": per_node, "alg_bytes_per_launch": alg_bytes,
+                     "kernel_ms": round(kms, 5)},
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(w),
         "mass": r32["mass"],
     }
+    out["source_hash"] = kernel_source_hash()
     print(json.dumps(out), flush=True)
 
 

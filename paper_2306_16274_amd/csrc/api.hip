@@ -42,10 +42,12 @@ struct lbm_ctx {
     int64_t steps = 0;
     Phys<double> pd{};
     Phys<float> pf{};
+    int fused_cfg = 0;             // index into kFusedCfgs
     std::string err;
 };
 
 static std::string g_create_error;
+static int default_fused_cfg(const lbm_ctx* c);
 
 static lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
     char buf[512];
@@ -64,6 +66,12 @@ static lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
             return fail((c), e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,       \
                         "%s failed: %s", #call, hipGetErrorString(e_));                  \
     } while (0)
+
+static long long plane_stride(long long N) { return (N + 63) / 64 * 64; }
+
+static size_t storage_bytes(int storage) {
+    return storage == LBM_FP64 ? 8 : storage == LBM_FP32 ? 4 : 2;
+}
 
 // ---------------------------------------------------------------------------------------
 // Equations of state on the host (float64), for validation and the coexistence solver.
@@ -169,11 +177,6 @@ extern "C" lbm_status lbm_params_default(lbm_params* p) {
     return LBM_OK;
 }
 
-static long long plane_stride(long long N) { return (N + 63) / 64 * 64; }
-
-static size_t storage_bytes(int storage) {
-    return storage == LBM_FP64 ? 8 : storage == LBM_FP32 ? 4 : 2;
-}
 
 extern "C" int64_t lbm_footprint_bytes(const lbm_params* p) {
     if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1) return -1;
@@ -207,6 +210,7 @@ static Phys<R> make_phys(const lbm_params& p) {
     return P;
 }
 
+
 static bool rate_ok(double s) { return s > 0.0 && s < 2.0 && std::isfinite(s); }
 
 static lbm_status validate(const lbm_params& p) {
@@ -236,6 +240,10 @@ static lbm_status validate(const lbm_params& p) {
     if (p.reduce_every < 0) return fail(nullptr, LBM_EINVAL, "reduce_every must be >= 0");
     if (p.step_kernel != LBM_STEP_FUSED && p.step_kernel != LBM_STEP_TWO_PASS)
         return fail(nullptr, LBM_EINVAL, "unknown step_kernel");
+    if (p.step_kernel == LBM_STEP_FUSED &&
+        (double)(p.lattice == 27 ? 27 : 19) * (double)plane_stride(N) * (double)storage_bytes(p.storage) >= 4294967296.0)
+        return fail(nullptr, LBM_EINVAL,
+                    "population buffer of 4 GiB or more: use step_kernel = LBM_STEP_TWO_PASS");
     return LBM_OK;
 }
 
@@ -262,17 +270,17 @@ static void build_solid(const lbm_params& p, std::vector<uint8_t>& s, bool& any)
 
 static void free_all(lbm_ctx* c) {
     if (!c) return;
-    hipSetDevice(c->device);
-    if (c->stream) hipStreamSynchronize(c->stream);
-    for (void* b : c->f) if (b) hipFree(b);
-    if (c->psi) hipFree(c->psi);
-    if (c->solid) hipFree(c->solid);
-    if (c->mom) hipFree(c->mom);
-    if (c->partial) hipFree(c->partial);
-    if (c->dtot) hipFree(c->dtot);
-    if (c->hhealth) hipHostFree(c->hhealth);
-    if (c->health_ev) hipEventDestroy(c->health_ev);
-    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (void* b : c->f) if (b) (void)hipFree(b);
+    if (c->psi) (void)hipFree(c->psi);
+    if (c->solid) (void)hipFree(c->solid);
+    if (c->mom) (void)hipFree(c->mom);
+    if (c->partial) (void)hipFree(c->partial);
+    if (c->dtot) (void)hipFree(c->dtot);
+    if (c->hhealth) (void)hipHostFree(c->hhealth);
+    if (c->health_ev) (void)hipEventDestroy(c->health_ev);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
 }
 
 extern "C" lbm_status lbm_create(const lbm_params* pp, lbm_ctx** out) {
@@ -292,6 +300,7 @@ extern "C" lbm_status lbm_create(const lbm_params* pp, lbm_ctx** out) {
     c->elem = storage_bytes(pp->storage);
     c->pd = make_phys<double>(*pp);
     c->pf = make_phys<float>(*pp);
+    c->fused_cfg = default_fused_cfg(c);
     auto bail = [&](lbm_status s) { g_create_error = c->err; free_all(c); delete c; return s; };
 #define CHK(call) do { hipError_t e_ = (call); if (e_ != hipSuccess) {                     \
         fail(c, e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "%s failed: %s", #call, \
@@ -356,7 +365,7 @@ static Grid grid_of(const lbm_ctx* c) {
 
 static lbm_status ensure_partial(lbm_ctx* c, long long n) {
     if (c->partial_cap >= n) return LBM_OK;
-    if (c->partial) { HIPCHK(c, hipStreamSynchronize(c->stream)); hipFree(c->partial); c->partial = nullptr; }
+    if (c->partial) { HIPCHK(c, hipStreamSynchronize(c->stream)); (void)hipFree(c->partial); c->partial = nullptr; }
     HIPCHK(c, hipMalloc(&c->partial, (size_t)n * sizeof(double)));
     c->partial_cap = n;
     return LBM_OK;
@@ -409,27 +418,67 @@ struct KernelTimer {
 static const char* const kTwoPassNames[] = {"k_density_psi", "k_collide"};
 static const char* const kFusedNames[] = {"k_step_fused"};
 
-constexpr int kTileX = 32, kTileY = 8;
+// Tile configurations of the fused kernel. 256 x 2 full rows: the x-shifted pulls of a
+// row stay inside one workgroup and the halo is two rows; 32 x 8 tiles for other widths.
+struct FusedCfg { int tx, ty; bool fullx, pipe; };
+static const FusedCfg kFusedCfgs[] = {
+    {32, 8, false, false}, {32, 8, false, true}, {256, 2, true, false}, {256, 2, true, true},
+    {64, 4, false, false}, {256, 4, true, false},
+};
+constexpr int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
 
-template <int Q, typename T>
-static void launch_fused(lbm_ctx* c, const void* fin, void* fout) {
+static int default_fused_cfg(const lbm_ctx* c) {
+    if (const char* e = getenv("LBM_FUSED_CONFIG")) {      // tuning override
+        const int v = atoi(e);
+        if (v >= 0 && v < kNumFusedCfgs && (!kFusedCfgs[v].fullx || c->p.nx == kFusedCfgs[v].tx))
+            return v;
+    }
+    if (c->p.nx == 256) return c->p.storage == LBM_FP64 ? 2 : 5;   // 256x4 needs <= 128 VGPRs
+    return 0;
+}
+
+// Planes per z-chunk and tile order. Full-row tiles: 64-plane chunks (about one
+// workgroup per CU slot at 256^3), dispatch order left as is. Small tiles: 16-plane
+// chunks, XCD-contiguous tile ranges (neighbouring tiles then share an L2). Measured on
+// MI355X at 256^3 (D3Q19, FP32 and FP64).
+static void fused_chunking(const lbm_ctx* c, int& zc, int& remap) {
+    const bool fullx = kFusedCfgs[c->fused_cfg].fullx;
+    zc = fullx ? 64 : 16;
+    remap = fullx ? 0 : 1;
+    if (const char* e = getenv("LBM_FUSED_ZC")) zc = std::max(1, atoi(e));      // tuning override
+    if (const char* e = getenv("LBM_FUSED_REMAP")) remap = atoi(e) != 0;       // tuning override
+    zc = std::min(zc, c->p.nz);
+}
+
+template <int Q, typename T, int TX, int TY, bool FULLX, bool PIPE>
+static void launch_fused_cfg(lbm_ctx* c, const void* fin, void* fout) {
     using R = typename Arith<T>::type;
     const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
                                                          ? (const void*)&c->pd : (const void*)&c->pf);
-    const int ntx = (c->p.nx + kTileX - 1) / kTileX, nty = (c->p.ny + kTileY - 1) / kTileY;
-    // about 4096 workgroups (16 per CU), chunks of at least 4 planes
+    const int ntx = (c->p.nx + TX - 1) / TX, nty = (c->p.ny + TY - 1) / TY;
     const long long tiles = (long long)ntx * nty;
-    long long nch = (4096 + tiles - 1) / tiles;
-    int zc = (int)((c->p.nz + nch - 1) / nch);
-    if (zc < 4) zc = std::min(4, c->p.nz);
+    int zc, remap;
+    fused_chunking(c, zc, remap);
     const int nchunks = (c->p.nz + zc - 1) / zc;
-    const dim3 grid((unsigned)(tiles * nchunks)), block(kTileX * kTileY);
+    const dim3 grid((unsigned)(tiles * nchunks)), block(TX * TY);
     if (c->any_solid)
-        hipLaunchKernelGGL((k_step_fused<Q, T, true, kTileX, kTileY>), grid, block, 0, c->stream,
-                           (const T*)fin, (T*)fout, c->solid, grid_of(c), P, ntx, nty, zc);
+        hipLaunchKernelGGL((k_step_fused<Q, T, true, TX, TY, FULLX, PIPE>), grid, block, 0, c->stream,
+                           (const T*)fin, (T*)fout, c->solid, grid_of(c), P, ntx, nty, zc, remap);
     else
-        hipLaunchKernelGGL((k_step_fused<Q, T, false, kTileX, kTileY>), grid, block, 0, c->stream,
-                           (const T*)fin, (T*)fout, c->solid, grid_of(c), P, ntx, nty, zc);
+        hipLaunchKernelGGL((k_step_fused<Q, T, false, TX, TY, FULLX, PIPE>), grid, block, 0, c->stream,
+                           (const T*)fin, (T*)fout, c->solid, grid_of(c), P, ntx, nty, zc, remap);
+}
+
+template <int Q, typename T>
+static void launch_fused(lbm_ctx* c, const void* fin, void* fout) {
+    switch (c->fused_cfg) {
+    case 1: launch_fused_cfg<Q, T, 32, 8, false, true>(c, fin, fout); break;
+    case 2: launch_fused_cfg<Q, T, 256, 2, true, false>(c, fin, fout); break;
+    case 3: launch_fused_cfg<Q, T, 256, 2, true, true>(c, fin, fout); break;
+    case 4: launch_fused_cfg<Q, T, 64, 4, false, false>(c, fin, fout); break;
+    case 5: launch_fused_cfg<Q, T, 256, 4, true, false>(c, fin, fout); break;
+    default: launch_fused_cfg<Q, T, 32, 8, false, false>(c, fin, fout); break;
+    }
 }
 
 template <int Q, typename T>
@@ -517,7 +566,7 @@ extern "C" lbm_status lbm_kernel_times(lbm_ctx* c, int64_t nsteps, double* avg_m
     KernelTimer tm{};
     for (int k = 0; k < 2 * KernelTimer::kMax; ++k) HIPCHK(c, hipEventCreate(&tm.ev[k]));
     lbm_status st = dispatch<StepFn>(c, nsteps, &tm);
-    for (int k = 0; k < 2 * KernelTimer::kMax; ++k) hipEventDestroy(tm.ev[k]);
+    for (int k = 0; k < 2 * KernelTimer::kMax; ++k) (void)hipEventDestroy(tm.ev[k]);
     if (st != LBM_OK) return st;
     const int n = std::min<int>(tm.nk, cap);
     for (int k = 0; k < n; ++k) {
@@ -621,7 +670,7 @@ struct PopFn {
             if (e == hipSuccess) e = hipMemcpyAsync(host, dbuf, bytes, hipMemcpyDeviceToHost, c->stream);
         }
         hipError_t e2 = hipStreamSynchronize(c->stream);
-        hipFree(dbuf);
+        (void)hipFree(dbuf);
         if (e != hipSuccess || e2 != hipSuccess)
             return fail(c, LBM_EDEVICE, "population transfer failed: %s",
                         hipGetErrorString(e != hipSuccess ? e : e2));

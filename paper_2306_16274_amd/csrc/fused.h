@@ -7,15 +7,20 @@
 //
 //   * a workgroup owns a TX x TY tile of (x, y) columns and marches along z over a chunk
 //     of planes [z0, z1); thread (lx, ly) owns column (x0+lx, y0+ly);
-//   * for the plane ahead (z+1) every thread pulls the Q populations of its own node
-//     into registers (they are collided one iteration later) and writes psi(rho) to an
-//     LDS ring of 4 planes; the first H threads also pull the populations of the
-//     2(TX+TY)+4 halo nodes of that plane, only to form their psi;
-//   * after one barrier the plane z is collided from registers with psi(z-1..z+1) read
-//     from LDS, and the post-collision populations are stored (SoA, coalesced);
-//   * halo pulls touch rows that the neighbouring tiles pull at about the same time:
-//     tiles are mapped to XCDs in contiguous ranges (workgroup b runs on XCD b mod 8),
-//     so neighbouring tiles share an L2 and the halo re-reads stay on chip.
+//   * psi of the planes z-1, z, z+1, z+2 lives in an LDS ring of four planes (tile plus
+//     halo); one barrier per plane;
+//   * software pipeline: at plane z a thread first issues the loads of its own node two
+//     planes ahead (z+2), then collides plane z from registers (loaded one iteration
+//     earlier) with psi(z-1..z+1) from LDS and stores it, and only then sums the
+//     z+2 populations into psi. The loads are in flight while the collision runs;
+//   * the first H = 2(TX+TY)+4 threads also pull the populations of the halo nodes of
+//     plane z+2, only to form their psi. Those rows are pulled by the neighbouring tiles
+//     at about the same time: tiles are mapped to XCDs in contiguous ranges (workgroup b
+//     runs on XCD b mod 8), so neighbouring tiles share an L2 and the halo re-reads stay
+//     on chip;
+//   * addresses are 32-bit byte offsets from the buffer base (the host checks that the
+//     population buffer is below 4 GiB), with the in-plane offsets of the 3x3 column
+//     neighbourhood computed once per thread.
 //
 // Every LDS cell stands for a node with periodically wrapped coordinates, so tiles that
 // cross the domain edge (or are wider than the domain) need no special case: threads
@@ -33,40 +38,65 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return xcd * q + (xcd < r ? xcd : r) + k;
 }
 
-// Pull the Q populations of node (x, y, z) (coordinates already wrapped) and return their
-// sum (the density deviation). SOLID: bounce back where the source is solid.
-template <int Q, typename T, typename R, bool SOLID, bool KEEP>
-__device__ __forceinline__ R pull_node(const T* __restrict__ f, const uint8_t* __restrict__ solid,
-                                       const Grid& g, int x, int y, int z, R* keep) {
-    int nb[Q];
-    neighbour_index<Q>(g, x, y, z, nb);
-    const int n = nb[0];
-    R s = 0;
+template <typename T>
+__device__ __forceinline__ T ld_off(const T* __restrict__ base, unsigned byte_off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void st_off(T* __restrict__ base, unsigned byte_off, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
+// Element index of the pull source x - e_i of population i for a column whose 3x3
+// in-plane neighbour indices are xy[(dy+1)*3 + dx+1] and whose plane indices are
+// zo[dz+1]; with bounce-back from the node itself when the source is solid.
+template <int Q, bool SOLID>
+__device__ __forceinline__ void pull_source(int i, const int* xy, const int* zo,
+                                            const uint8_t* __restrict__ solid, int& e, int& pop) {
+    e = xy[(1 - vel_y(i)) * 3 + (1 - vel_x(i))] + zo[1 - vel_z(i)];
+    pop = i;
+    if (SOLID && i != 0 && solid[e]) { e = xy[4] + zo[1]; pop = opposite(i); }
+}
+
+// Issue the Q loads of a column's node (values land in v[]).
+template <int Q, typename T, typename R, bool SOLID>
+__device__ __forceinline__ void pull_loads(const T* __restrict__ f, const uint8_t* __restrict__ solid,
+                                           const int* xy, const int* zo, unsigned pst, R* v) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const int o = opposite(i);
-        long long idx = (long long)i * g.stride + nb[o];
-        if (SOLID && i != 0 && solid[nb[o]]) idx = (long long)o * g.stride + n;
-        const R v = load_as<T, R>(f + idx);
-        if (KEEP) keep[i] = v;
-        s += v;
+        int e, pop;
+        pull_source<Q, SOLID>(i, xy, zo, solid, e, pop);
+        v[i] = static_cast<R>(ld_off(f, (unsigned)e * (unsigned)sizeof(T) + (unsigned)pop * pst));
     }
+}
+
+template <int Q, typename R>
+__device__ __forceinline__ R sum_q(const R* v) {
+    R s = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) s += v[i];
     return s;
 }
 
-template <int Q, typename T, bool SOLID, int TX, int TY>
+// FULLX: the tile spans the whole x extent (TX == nx); x wraps inside the tile and the
+// halo is just the rows y0-1 and y0+TY (H = 2 TX, one halo node per thread when TY = 2).
+// PIPE: prefetch the own node two planes ahead (three register sets) so that its loads
+// overlap the collision of the current plane.
+// REMAP: map workgroups to tiles so that each XCD gets a contiguous tile range.
+template <int Q, typename T, bool SOLID, int TX, int TY, bool FULLX, bool PIPE>
 __global__ __launch_bounds__(TX * TY) void k_step_fused(const T* __restrict__ fin,
                                                        T* __restrict__ fout,
                                                        const uint8_t* __restrict__ solid,
                                                        Grid g, Phys<typename Arith<T>::type> P,
-                                                       int ntx, int nty, int zc) {
+                                                       int ntx, int nty, int zc, int remap) {
     using R = typename Arith<T>::type;
-    constexpr int LX = TX + 2, LY = TY + 2;
-    constexpr int H = 2 * (TX + TY) + 4;
+    constexpr int LX = FULLX ? TX : TX + 2, LY = TY + 2;
+    constexpr int OX = FULLX ? 0 : 1;                 // LDS column of tile column 0
+    constexpr int H = FULLX ? 2 * TX : 2 * (TX + TY) + 4;
     static_assert(H <= TX * TY, "halo larger than the workgroup");
     __shared__ R ring[4][LY][LX];
 
-    int t = xcd_tile(blockIdx.x, gridDim.x);
+    int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int ix = t % ntx; t /= ntx;
     const int iy = t % nty;
     const int iz = t / nty;
@@ -77,62 +107,122 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(const T* __restrict__ fi
     const int x = x0 + lx, y = y0 + ly;
     const bool active = x < g.nx && y < g.ny;
     auto wrapc = [](int c, int n) { c %= n; return c < 0 ? c + n : c; };
-    const int xw = wrapc(x, g.nx), yw = wrapc(y, g.ny);
+    const int nxy = g.nx * g.ny;
+    const unsigned pst = (unsigned)g.stride * (unsigned)sizeof(T);   // plane stride, bytes
 
-    // halo cell of this thread (if any), as LDS coordinates (hx, hy) in [-1, T]
+    // halo cell of this thread (if any), as tile coordinates (hx, hy)
     int hx = 0, hy = 0;
     const bool has_halo = tid < H;
     if (has_halo) {
-        if (tid < LX) { hx = tid - 1; hy = -1; }
+        if (FULLX) { hx = tid % TX; hy = tid < TX ? -1 : TY; }
+        else if (tid < LX) { hx = tid - 1; hy = -1; }
         else if (tid < 2 * LX) { hx = tid - LX - 1; hy = TY; }
         else if (tid < 2 * LX + TY) { hx = -1; hy = tid - 2 * LX; }
         else { hx = TX; hy = tid - 2 * LX - TY; }
     }
-    const int hxw = wrapc(x0 + hx, g.nx), hyw = wrapc(y0 + hy, g.ny);
-
-    auto psi_of = [&](R drho) { return pseudopotential<R>(P.rho_ref + drho, P); };
-    auto plane_psi = [&](int zp, int slot, R* keep) {
-        // own node (populations kept when keep != nullptr)
-        const int zw = wrapc(zp, g.nz);
-        R v;
-        if (SOLID && solid[xw + g.nx * (yw + g.ny * zw)]) v = R(-1);
-        else if (keep) v = psi_of(pull_node<Q, T, R, SOLID, true>(fin, solid, g, xw, yw, zw, keep));
-        else v = psi_of(pull_node<Q, T, R, SOLID, false>(fin, solid, g, xw, yw, zw, nullptr));
-        ring[slot][ly + 1][lx + 1] = v;
-        if (has_halo) {
-            R hv;
-            if (SOLID && solid[hxw + g.nx * (hyw + g.ny * zw)]) hv = R(-1);
-            else hv = psi_of(pull_node<Q, T, R, SOLID, false>(fin, solid, g, hxw, hyw, zw, nullptr));
-            ring[slot][hy + 1][hx + 1] = hv;
+    // in-plane indices of the 3x3 neighbourhood of the own column and of the halo column
+    int oxy[9], hxy[9];
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            oxy[(dy + 1) * 3 + dx + 1] = wrapc(x + dx, g.nx) + wrapc(y + dy, g.ny) * g.nx;
+            hxy[(dy + 1) * 3 + dx + 1] =
+                wrapc(x0 + hx + dx, g.nx) + wrapc(y0 + hy + dy, g.ny) * g.nx;
         }
+    auto zoffs = [&](int zp, int* zo) {
+        zo[0] = wrapc(zp - 1, g.nz) * nxy;
+        zo[1] = wrapc(zp, g.nz) * nxy;
+        zo[2] = wrapc(zp + 1, g.nz) * nxy;
     };
-
-    R cur[Q], nxt[Q];
-    plane_psi(z0 - 1, 0, nullptr);
-    plane_psi(z0, 1, cur);
-
-    for (int z = z0; z < z1; ++z) {
-        const int k = z - z0;
-        plane_psi(z + 1, (k + 2) & 3, nxt);
-        __syncthreads();
-        const int s0 = k & 3, s1 = (k + 1) & 3, s2 = (k + 2) & 3;
-        const R psi0 = ring[s1][ly + 1][lx + 1];
+    auto psi_of = [&](R drho) { return pseudopotential<R>(P.rho_ref + drho, P); };
+    // psi of the halo node of plane zp into ring slot
+    auto halo_psi = [&](int zp, int slot) {
+        if (!has_halo) return;
+        int zo[3];
+        zoffs(zp, zo);
+        R hv;
+        if (SOLID && solid[hxy[4] + zo[1]]) hv = R(-1);
+        else {
+            R v[Q];
+            pull_loads<Q, T, R, SOLID>(fin, solid, hxy, zo, pst, v);
+            hv = psi_of(sum_q<Q, R>(v));
+        }
+        ring[slot][hy + 1][hx + OX] = hv;
+    };
+    // own node of plane zp: loads into v, psi into ring slot
+    auto own_psi = [&](int zp, int slot, R* v) {
+        int zo[3];
+        zoffs(zp, zo);
+        const bool s = SOLID && solid[oxy[4] + zo[1]];
+        pull_loads<Q, T, R, SOLID>(fin, solid, oxy, zo, pst, v);
+        ring[slot][ly + 1][lx + OX] = s ? R(-1) : psi_of(sum_q<Q, R>(v));
+    };
+    // LDS column of tile column lx + dx
+    auto col = [&](int dx) {
+        if (!FULLX) return lx + 1 + dx;
+        const int c = lx + dx;
+        return c < 0 ? c + TX : (c >= TX ? c - TX : c);
+    };
+    auto collide_store = [&](R* c, int z, int s0, int s1, int s2) {
+        const R psi0 = ring[s1][ly + 1][lx + OX];
         if (active && !(psi0 < R(0))) {
             R pn[Q];
 #pragma unroll
             for (int j = 0; j < Q; ++j) {
                 const int ez = vel_z(j);
                 const int sl = ez < 0 ? s0 : (ez > 0 ? s2 : s1);
-                pn[j] = ring[sl][ly + 1 + vel_y(j)][lx + 1 + vel_x(j)];
+                pn[j] = ring[sl][ly + 1 + vel_y(j)][col(vel_x(j))];
             }
             const NodeForce<R> nf = node_force<Q, R>(psi0, pn, P);
-            collide<Q, R>(cur, nf, P);
-            const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
+            collide<Q, R>(c, nf, P);
+            const unsigned nb = (unsigned)(oxy[4] + z * nxy) * (unsigned)sizeof(T);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) store_as<T, R>(fout + (long long)i * g.stride + n, cur[i]);
+            for (int i = 0; i < Q; ++i) st_off(fout, nb + (unsigned)i * pst, static_cast<T>(c[i]));
         }
+    };
+
+    if (PIPE) {
+        R c0[Q], c1[Q], c2[Q];
+        own_psi(z0 - 1, 0, c2);
+        halo_psi(z0 - 1, 0);
+        own_psi(z0, 1, c0);
+        halo_psi(z0, 1);
+        own_psi(z0 + 1, 2, c1);
+        halo_psi(z0 + 1, 2);
+        __syncthreads();
+        for (int z = z0; z < z1; ++z) {
+            const int k = z - z0;
+            const bool more = z + 1 < z1;        // plane z+1 is collided next: psi(z+2) needed
+            int zo2[3];
+            zoffs(z + 2, zo2);
+            if (more) pull_loads<Q, T, R, SOLID>(fin, solid, oxy, zo2, pst, c2);
+            collide_store(c0, z, k & 3, (k + 1) & 3, (k + 2) & 3);
+            if (more) {
+                const int s3 = (k + 3) & 3;
+                const bool s = SOLID && solid[oxy[4] + zo2[1]];
+                ring[s3][ly + 1][lx + OX] = s ? R(-1) : psi_of(sum_q<Q, R>(c2));
+                halo_psi(z + 2, s3);
+            }
+            __syncthreads();
 #pragma unroll
-        for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
+            for (int i = 0; i < Q; ++i) { c0[i] = c1[i]; c1[i] = c2[i]; }
+        }
+    } else {
+        R cur[Q], nxt[Q];
+        own_psi(z0 - 1, 0, nxt);
+        halo_psi(z0 - 1, 0);
+        own_psi(z0, 1, cur);
+        halo_psi(z0, 1);
+        for (int z = z0; z < z1; ++z) {
+            const int k = z - z0;
+            own_psi(z + 1, (k + 2) & 3, nxt);
+            halo_psi(z + 1, (k + 2) & 3);
+            __syncthreads();
+            collide_store(cur, z, k & 3, (k + 1) & 3, (k + 2) & 3);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
+        }
     }
 }
 

@@ -61,6 +61,13 @@ __host__ __device__ constexpr double wforce(int i) { return 3.0 * omega<Q>(i); }
 
 enum { EOS_CS = 0, EOS_PIECEWISE = 1 };
 
+// Reciprocal and square root: in float32 the hardware instructions (v_rcp_f32,
+// v_sqrt_f32, about 1 ulp); in float64 the correctly rounded operations.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float sqrt_r(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+
 // Physical constants of one lattice, in the arithmetic type R.
 template <typename R>
 struct Phys {
@@ -84,7 +91,7 @@ __device__ __forceinline__ R pseudopotential(R rho, const Phys<R>& P) {
     if (P.eos == EOS_CS) {
         const R eta = P.cs_b * rho * R(0.25);
         const R om = R(1) - eta;
-        p = rho * P.cs_RT * (R(1) + eta + eta * eta - eta * eta * eta) / (om * om * om) -
+        p = rho * P.cs_RT * (R(1) + eta + eta * eta - eta * eta * eta) * recip(om * om * om) -
             P.cs_a * rho * rho;
     } else {
         p = rho <= P.pw_r1 ? rho * P.pw_tv
@@ -92,7 +99,7 @@ __device__ __forceinline__ R pseudopotential(R rho, const Phys<R>& P) {
                              : P.pw_p2 + (rho - P.pw_r2) * P.pw_tl;
     }
     const R arg = P.two_over_G * (p - rho * R(1.0 / 3.0));
-    return arg > R(0) ? sqrt(arg) : R(0);
+    return arg > R(0) ? sqrt_r(arg) : R(0);
 }
 
 // Force terms at one node from psi at the node and its Q-1 neighbours.
@@ -265,7 +272,7 @@ template <int Q, typename R>
 __device__ __forceinline__ R collide(R* d, const NodeForce<R>& nf, const Phys<R>& P) {
     const Raw<R> k = forward<Q, R>(d);
     const R rho = P.rho_ref + k.k000;
-    const R inv_rho = R(1) / rho;
+    const R inv_rho = recip(rho);
     const R Fx = nf.Fx, Fy = nf.Fy, Fz = nf.Fz;
     const R ux = (k.k100 + R(0.5) * Fx) * inv_rho;
     const R uy = (k.k010 + R(0.5) * Fy) * inv_rho;
@@ -276,7 +283,7 @@ __device__ __forceinline__ R collide(R* d, const NodeForce<R>& nf, const Phys<R>
     R s_nu = P.s_nu;
     if (P.var_nu) {   // Eq. (24) with nu = (1/s_nu - 1/2)/3
         const R nu = P.nu_v + P.dnu_drho * (rho - P.rho_v);
-        s_nu = R(1) / (R(3) * nu + R(0.5));
+        s_nu = recip(R(3) * nu + R(0.5));
     }
     const R sn = s_nu, hn = R(1) - R(0.5) * sn;
     const R se = P.s_e, he = R(1) - R(0.5) * se;
