@@ -160,6 +160,34 @@ lbm_status lbm_coexistence(const lbm_params* p, double* rho_v, double* rho_l);
 /* Device bytes a context created from *p allocates (for admission control), or -1.    */
 int64_t lbm_footprint_bytes(const lbm_params* p);
 
+/*
+ * Batched stepping (serving many independent lattices). A batch holds a fixed set of
+ * contexts (D3Q19, all FP32 or all FP64 storage, each initialised) and advances all of
+ * them together: one kernel launch per time step covers the tiles of every member, and
+ * steps_per_launch consecutive launches are captured once into a HIP graph. Each member
+ * takes exactly the time step of lbm_step (same results up to rounding order).
+ * The batch borrows the contexts (they must outlive it and must not be stepped on their
+ * own while the batch runs); it orders its work after, and each member's later work
+ * after, the batch's graph launches through events.
+ */
+typedef struct lbm_batch lbm_batch;
+
+/* Build a batch of n distinct contexts. steps_per_launch: even, >= 2 (time steps per
+   graph replay). stream: hipStream_t for the replays, or NULL for a batch-owned stream.
+   Does not wait for the members' pending work (lbm_batch_run orders after it).         */
+lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, int32_t steps_per_launch,
+                            void* stream, lbm_batch** out);
+
+/* Advance every member by nlaunch * steps_per_launch time steps (asynchronous).        */
+lbm_status lbm_batch_run(lbm_batch* b, int64_t nlaunch);
+
+/* Release the batch (not the member contexts): waits for the batch's own replays only.
+   NULL is accepted.                                                                     */
+lbm_status lbm_batch_destroy(lbm_batch* b);
+
+/* Message of the last failed lbm_batch_* call.                                          */
+const char* lbm_batch_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

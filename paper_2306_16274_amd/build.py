@@ -11,6 +11,9 @@ HEADERS = ["lattice.h", "kernels.h", "../../include/lbm.h"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",
+    # fuse a*b+c only where the source writes it in one expression: the rounding of a node
+    # update then does not depend on the kernel it is inlined into (tile shape, batching)
+    "-ffp-contract=on",
     "--offload-arch=gfx950",
     # no packed FP32 instructions (v_pk_*_f32) anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -73,6 +73,12 @@ static size_t storage_bytes(int storage) {
     return storage == LBM_FP64 ? 8 : storage == LBM_FP32 ? 4 : 2;
 }
 
+// Device buffers of a context are allocated and freed in stream order on the context's
+// stream (hipMallocAsync / hipFreeAsync), so creating or destroying one lattice never
+// waits for the work of other lattices.
+static hipError_t dmalloc(hipStream_t s, void** p, size_t bytes) { return hipMallocAsync(p, bytes, s); }
+static void dfree(hipStream_t s, void* p) { if (p) (void)hipFreeAsync(p, s); }
+
 // ---------------------------------------------------------------------------------------
 // Equations of state on the host (float64), for validation and the coexistence solver.
 static double eos_p(const lbm_params& p, double rho) {
@@ -93,14 +99,15 @@ static double eos_rho_max(const lbm_params& p) {
     return p.eos == LBM_EOS_CS ? 0.999 * 4.0 / p.cs_b : 50.0;
 }
 
-// integral of p(rho)/rho^2 over [a, b] with composite 8-point Gauss-Legendre in ln(rho)
-static double int_p_over_rho2(const lbm_params& p, double a, double b) {
+// integral of p(rho)/rho^2 over [a, b] with composite 8-point Gauss-Legendre in ln(rho);
+// for the piecewise EOS the interval is split at its knees (p is only piecewise smooth)
+static double int_smooth(const lbm_params& p, double a, double b) {
     static const double xg[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267,
                                  0.9602898564975363};
     static const double wg[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745,
                                  0.1012285362903763};
     const double la = std::log(a), lb = std::log(b);
-    const int panels = 400;
+    const int panels = 64;
     const double hw = (lb - la) / panels;
     double s = 0;
     for (int k = 0; k < panels; ++k) {
@@ -115,21 +122,41 @@ static double int_p_over_rho2(const lbm_params& p, double a, double b) {
     return s;
 }
 
+static double int_p_over_rho2(const lbm_params& p, double a, double b) {
+    if (p.eos != LBM_EOS_PIECEWISE) return int_smooth(p, a, b);
+    double cuts[4] = {a, 0, 0, b};
+    int n = 1;
+    for (double k : {p.pw_rho1, p.pw_rho2})
+        if (k > a && k < b) cuts[n++] = k;
+    cuts[n++] = b;
+    double s = 0;
+    for (int i = 0; i + 1 < n; ++i) s += int_smooth(p, cuts[i], cuts[i + 1]);
+    return s;
+}
+
 extern "C" lbm_status lbm_coexistence(const lbm_params* pp, double* rho_v, double* rho_l) {
     if (!pp || !rho_v || !rho_l) return fail(nullptr, LBM_EINVAL, "null argument");
     const lbm_params& p = *pp;
     const double hi = eos_rho_max(p), lo = 1e-9;
-    // spinodals: scan dp/drho for the unstable branch
-    const int M = 200000;
+    // spinodals: sample dp/drho for the unstable branch, refine the sign changes by bisection
+    const int M = 4000;
     auto dp = [&](double r) { const double h = 1e-7 * std::max(r, 1e-6);
                               return (eos_p(p, r + h) - eos_p(p, r - h)) / (2 * h); };
+    auto refine = [&](double a, double b) {       // dp changes sign in [a, b]
+        const bool sa = dp(a) < 0;
+        for (int it = 0; it < 60; ++it) {
+            const double m = 0.5 * (a + b);
+            if ((dp(m) < 0) == sa) a = m; else b = m;
+        }
+        return 0.5 * (a + b);
+    };
     double s_lo = -1, s_hi = -1, prev = dp(lo);
     double rprev = lo;
     for (int k = 1; k <= M; ++k) {
         const double r = lo + (hi - lo) * k / M;
         const double v = dp(r);
-        if (prev >= 0 && v < 0 && s_lo < 0) s_lo = 0.5 * (r + rprev);
-        if (prev < 0 && v >= 0) s_hi = 0.5 * (r + rprev);
+        if (prev >= 0 && v < 0 && s_lo < 0) s_lo = refine(rprev, r);
+        if (prev < 0 && v >= 0) s_hi = refine(rprev, r);
         prev = v; rprev = r;
     }
     if (s_lo < 0 || s_hi < 0)
@@ -137,7 +164,7 @@ extern "C" lbm_status lbm_coexistence(const lbm_params* pp, double* rho_v, doubl
     const double pmax = eos_p(p, s_lo), pmin = std::max(eos_p(p, s_hi), eos_p(p, lo));
     auto root = [&](double p0, double a, double b) {   // p(r) = p0 on a monotone branch
         double fa = eos_p(p, a) - p0;
-        for (int it = 0; it < 200; ++it) {
+        for (int it = 0; it < 100; ++it) {
             const double m = 0.5 * (a + b), fm = eos_p(p, m) - p0;
             if ((fm < 0) == (fa < 0)) { a = m; fa = fm; } else b = m;
         }
@@ -150,10 +177,10 @@ extern "C" lbm_status lbm_coexistence(const lbm_params* pp, double* rho_v, doubl
     };
     double a = pmin + 1e-12 * std::fabs(pmax), b = pmax - 1e-12 * std::fabs(pmax), rv, rl;
     double fa = area(a, &rv, &rl);
-    for (int it = 0; it < 200; ++it) {
+    for (int it = 0; it < 80; ++it) {
         const double m = 0.5 * (a + b), fm = area(m, &rv, &rl);
         if ((fm < 0) == (fa < 0)) { a = m; fa = fm; } else b = m;
-        if (b - a < 1e-17) break;
+        if (b - a <= 1e-16 * std::fabs(pmax)) break;
     }
     area(0.5 * (a + b), &rv, &rl);
     *rho_v = rv; *rho_l = rl;
@@ -247,37 +274,76 @@ static lbm_status validate(const lbm_params& p) {
     return LBM_OK;
 }
 
-static void build_solid(const lbm_params& p, std::vector<uint8_t>& s, bool& any) {
-    const long long N = (long long)p.nx * p.ny * p.nz;
-    s.assign(N, 0);
-    any = false;
+// ---------------------------------------------------------------------------------------
+// Launch helpers
+struct Launch { dim3 grid, block; };
+static Launch node_launch(const lbm_ctx* c) {
+    Launch L;
+    const int bx = c->p.nx >= 64 ? 64 : (c->p.nx >= 32 ? 32 : 16);
+    const int by = 256 / bx;
+    L.block = dim3(bx, by, 1);
+    L.grid = dim3((c->p.nx + bx - 1) / bx, (c->p.ny + by - 1) / by, c->p.nz);
+    return L;
+}
+static long long nblocks(const Launch& L) { return (long long)L.grid.x * L.grid.y * L.grid.z; }
+
+static Grid grid_of(const lbm_ctx* c) {
+    Grid g;
+    g.nx = c->p.nx; g.ny = c->p.ny; g.nz = c->p.nz; g.stride = c->stride;
+    g.walls = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int s = 0; s < 2; ++s)
+            if (c->p.bc[a][s] == LBM_BC_WALL) g.walls |= 1 << (2 * a + s);
+    return g;
+}
+
+// Solid-node source of the fused kernels: none, wall layers from coordinates, or mask.
+static int geom_of(const lbm_ctx* c) {
+    if (!c->any_solid) return GEOM_NONE;
+    return c->p.cylinder ? GEOM_MASK : GEOM_WALLS;
+}
+
+// Solid nodes: wall layers on the faces marked LBM_BC_WALL and the nodes whose centre lies
+// in the x-aligned cylinder. The mask is written on the device (k_build_solid, the same
+// predicate); the host only counts solid nodes, from one (y, z) plane since the geometry
+// does not depend on x except through the x walls.
+static bool solid_yz(const lbm_params& p, int y, int z) {
+    if (p.bc[1][0] == LBM_BC_WALL && y == 0) return true;
+    if (p.bc[1][1] == LBM_BC_WALL && y == p.ny - 1) return true;
+    if (p.bc[2][0] == LBM_BC_WALL && z == 0) return true;
+    if (p.bc[2][1] == LBM_BC_WALL && z == p.nz - 1) return true;
+    if (p.cylinder) {
+        const double dy = y - p.cyl_y, dz = z - p.cyl_z;
+        if (dy * dy + dz * dz <= p.cyl_r * p.cyl_r) return true;
+    }
+    return false;
+}
+
+static long long count_fluid(const lbm_params& p, bool& any_solid) {
+    long long yz_fluid = 0;
     for (int z = 0; z < p.nz; ++z)
-        for (int y = 0; y < p.ny; ++y)
-            for (int x = 0; x < p.nx; ++x) {
-                bool sol = false;
-                const int c[3] = {x, y, z}, n[3] = {p.nx, p.ny, p.nz};
-                for (int a = 0; a < 3; ++a) {
-                    if (p.bc[a][0] == LBM_BC_WALL && c[a] == 0) sol = true;
-                    if (p.bc[a][1] == LBM_BC_WALL && c[a] == n[a] - 1) sol = true;
-                }
-                if (p.cylinder) {
-                    const double dy = y - p.cyl_y, dz = z - p.cyl_z;
-                    if (dy * dy + dz * dz <= p.cyl_r * p.cyl_r) sol = true;
-                }
-                if (sol) { s[x + (long long)p.nx * (y + (long long)p.ny * z)] = 1; any = true; }
-            }
+        for (int y = 0; y < p.ny; ++y) yz_fluid += !solid_yz(p, y, z);
+    int x_fluid = p.nx;
+    if (p.bc[0][0] == LBM_BC_WALL) --x_fluid;
+    if (p.bc[0][1] == LBM_BC_WALL && p.nx > 1) --x_fluid;
+    x_fluid = std::max(x_fluid, 0);
+    const long long fluid = yz_fluid * x_fluid;
+    any_solid = fluid != (long long)p.nx * p.ny * p.nz;
+    return fluid;
 }
 
 static void free_all(lbm_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
-    for (void* b : c->f) if (b) (void)hipFree(b);
-    if (c->psi) (void)hipFree(c->psi);
-    if (c->solid) (void)hipFree(c->solid);
-    if (c->mom) (void)hipFree(c->mom);
-    if (c->partial) (void)hipFree(c->partial);
-    if (c->dtot) (void)hipFree(c->dtot);
+    if (c->stream) {
+        for (void* b : c->f) dfree(c->stream, b);
+        dfree(c->stream, c->psi);
+        dfree(c->stream, c->solid);
+        dfree(c->stream, c->mom);
+        dfree(c->stream, c->partial);
+        dfree(c->stream, c->dtot);
+        (void)hipStreamSynchronize(c->stream);      // this lattice's work only
+    }
     if (c->hhealth) (void)hipHostFree(c->hhealth);
     if (c->health_ev) (void)hipEventDestroy(c->health_ev);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -310,22 +376,25 @@ extern "C" lbm_status lbm_create(const lbm_params* pp, lbm_ctx** out) {
     if (pp->stream) c->stream = (hipStream_t)pp->stream;
     else { CHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)); c->own_stream = true; }
     const size_t fbytes = (size_t)c->Q * c->stride * c->elem;
-    CHK(hipMalloc(&c->f[0], fbytes));
-    CHK(hipMalloc(&c->f[1], fbytes));
+    CHK(dmalloc(c->stream, &c->f[0], fbytes));
+    CHK(dmalloc(c->stream, &c->f[1], fbytes));
     CHK(hipMemsetAsync(c->f[0], 0, fbytes, c->stream));
     CHK(hipMemsetAsync(c->f[1], 0, fbytes, c->stream));
-    CHK(hipMalloc(&c->psi, (size_t)c->N * (pp->storage == LBM_FP64 ? 8 : 4)));
-    CHK(hipMalloc(&c->solid, (size_t)c->N));
-    std::vector<uint8_t> s;
-    build_solid(*pp, s, c->any_solid);
-    long long nfluid = 0;
-    for (uint8_t v : s) nfluid += !v;
-    if (nfluid == 0) { fail(c, LBM_EINVAL, "geometry leaves no fluid node"); return bail(LBM_EINVAL); }
-    CHK(hipMemcpyAsync(c->solid, s.data(), (size_t)c->N, hipMemcpyHostToDevice, c->stream));
-    CHK(hipMalloc(&c->dtot, 8 * sizeof(double)));
+    CHK(dmalloc(c->stream, &c->psi, (size_t)c->N * (pp->storage == LBM_FP64 ? 8 : 4)));
+    CHK(dmalloc(c->stream, (void**)&c->solid, (size_t)c->N));
+    if (count_fluid(*pp, c->any_solid) == 0) {
+        fail(c, LBM_EINVAL, "geometry leaves no fluid node");
+        return bail(LBM_EINVAL);
+    }
+    {
+        const Launch L = node_launch(c);
+        hipLaunchKernelGGL(k_build_solid, L.grid, L.block, 0, c->stream, c->solid, grid_of(c),
+                           pp->cylinder, pp->cyl_y, pp->cyl_z, pp->cyl_r);
+        CHK(hipGetLastError());
+    }
+    CHK(dmalloc(c->stream, (void**)&c->dtot, 8 * sizeof(double)));
     CHK(hipHostMalloc((void**)&c->hhealth, 2 * sizeof(double), hipHostMallocDefault));
     CHK(hipEventCreateWithFlags(&c->health_ev, hipEventDisableTiming));
-    CHK(hipStreamSynchronize(c->stream));
 #undef CHK
     *out = c;
     return LBM_OK;
@@ -344,29 +413,11 @@ extern "C" const char* lbm_last_error(const lbm_ctx* c) {
 
 extern "C" int64_t lbm_steps_done(const lbm_ctx* c) { return c ? c->steps : -1; }
 
-// ---------------------------------------------------------------------------------------
-// Launch helpers
-struct Launch { dim3 grid, block; };
-static Launch node_launch(const lbm_ctx* c) {
-    Launch L;
-    const int bx = c->p.nx >= 64 ? 64 : (c->p.nx >= 32 ? 32 : 16);
-    const int by = 256 / bx;
-    L.block = dim3(bx, by, 1);
-    L.grid = dim3((c->p.nx + bx - 1) / bx, (c->p.ny + by - 1) / by, c->p.nz);
-    return L;
-}
-static long long nblocks(const Launch& L) { return (long long)L.grid.x * L.grid.y * L.grid.z; }
-
-static Grid grid_of(const lbm_ctx* c) {
-    Grid g;
-    g.nx = c->p.nx; g.ny = c->p.ny; g.nz = c->p.nz; g.stride = c->stride;
-    return g;
-}
-
 static lbm_status ensure_partial(lbm_ctx* c, long long n) {
     if (c->partial_cap >= n) return LBM_OK;
-    if (c->partial) { HIPCHK(c, hipStreamSynchronize(c->stream)); (void)hipFree(c->partial); c->partial = nullptr; }
-    HIPCHK(c, hipMalloc(&c->partial, (size_t)n * sizeof(double)));
+    dfree(c->stream, c->partial);
+    c->partial = nullptr;
+    HIPCHK(c, dmalloc(c->stream, (void**)&c->partial, (size_t)n * sizeof(double)));
     c->partial_cap = n;
     return LBM_OK;
 }
@@ -420,11 +471,8 @@ static const char* const kFusedNames[] = {"k_step_fused"};
 
 // Tile configurations of the fused kernel. 256 x 2 full rows: the x-shifted pulls of a
 // row stay inside one workgroup and the halo is two rows; 32 x 8 tiles for other widths.
-struct FusedCfg { int tx, ty; bool fullx, pipe; };
-static const FusedCfg kFusedCfgs[] = {
-    {32, 8, false, false}, {32, 8, false, true}, {256, 2, true, false}, {256, 2, true, true},
-    {64, 4, false, false}, {256, 4, true, false},
-};
+struct FusedCfg { int tx, ty; bool fullx; };
+static const FusedCfg kFusedCfgs[] = {{32, 8, false}, {256, 2, true}, {256, 4, true}};
 constexpr int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
 
 static int default_fused_cfg(const lbm_ctx* c) {
@@ -433,7 +481,7 @@ static int default_fused_cfg(const lbm_ctx* c) {
         if (v >= 0 && v < kNumFusedCfgs && (!kFusedCfgs[v].fullx || c->p.nx == kFusedCfgs[v].tx))
             return v;
     }
-    if (c->p.nx == 256) return c->p.storage == LBM_FP64 ? 2 : 5;   // 256x4 needs <= 128 VGPRs
+    if (c->p.nx == 256) return c->p.storage == LBM_FP64 ? 1 : 2;   // 256x4 needs <= 128 VGPRs
     return 0;
 }
 
@@ -450,7 +498,7 @@ static void fused_chunking(const lbm_ctx* c, int& zc, int& remap) {
     zc = std::min(zc, c->p.nz);
 }
 
-template <int Q, typename T, int TX, int TY, bool FULLX, bool PIPE>
+template <int Q, typename T, int TX, int TY, bool FULLX>
 static void launch_fused_cfg(lbm_ctx* c, const void* fin, void* fout) {
     using R = typename Arith<T>::type;
     const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
@@ -461,23 +509,31 @@ static void launch_fused_cfg(lbm_ctx* c, const void* fin, void* fout) {
     fused_chunking(c, zc, remap);
     const int nchunks = (c->p.nz + zc - 1) / zc;
     const dim3 grid((unsigned)(tiles * nchunks)), block(TX * TY);
-    if (c->any_solid)
-        hipLaunchKernelGGL((k_step_fused<Q, T, true, TX, TY, FULLX, PIPE>), grid, block, 0, c->stream,
-                           (const T*)fin, (T*)fout, c->solid, grid_of(c), P, ntx, nty, zc, remap);
-    else
-        hipLaunchKernelGGL((k_step_fused<Q, T, false, TX, TY, FULLX, PIPE>), grid, block, 0, c->stream,
-                           (const T*)fin, (T*)fout, c->solid, grid_of(c), P, ntx, nty, zc, remap);
+    // the kernel addresses populations with 32-bit byte offsets (checked at create)
+    switch (geom_of(c)) {
+    case GEOM_NONE:
+        hipLaunchKernelGGL((k_step_fused<Q, T, GEOM_NONE, TX, TY, FULLX>), grid, block, 0,
+                           c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), P, ntx, nty,
+                           zc, remap);
+        break;
+    case GEOM_WALLS:
+        hipLaunchKernelGGL((k_step_fused<Q, T, GEOM_WALLS, TX, TY, FULLX>), grid, block, 0,
+                           c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), P, ntx, nty,
+                           zc, remap);
+        break;
+    default:
+        hipLaunchKernelGGL((k_step_fused<Q, T, GEOM_MASK, TX, TY, FULLX>), grid, block, 0,
+                           c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), P, ntx, nty,
+                           zc, remap);
+    }
 }
 
 template <int Q, typename T>
 static void launch_fused(lbm_ctx* c, const void* fin, void* fout) {
     switch (c->fused_cfg) {
-    case 1: launch_fused_cfg<Q, T, 32, 8, false, true>(c, fin, fout); break;
-    case 2: launch_fused_cfg<Q, T, 256, 2, true, false>(c, fin, fout); break;
-    case 3: launch_fused_cfg<Q, T, 256, 2, true, true>(c, fin, fout); break;
-    case 4: launch_fused_cfg<Q, T, 64, 4, false, false>(c, fin, fout); break;
-    case 5: launch_fused_cfg<Q, T, 256, 4, true, false>(c, fin, fout); break;
-    default: launch_fused_cfg<Q, T, 32, 8, false, false>(c, fin, fout); break;
+    case 1: launch_fused_cfg<Q, T, 256, 2, true>(c, fin, fout); break;
+    case 2: launch_fused_cfg<Q, T, 256, 4, true>(c, fin, fout); break;
+    default: launch_fused_cfg<Q, T, 32, 8, false>(c, fin, fout); break;
     }
 }
 
@@ -602,7 +658,7 @@ struct InitFieldsFn {
 
 static lbm_status ensure_mom(lbm_ctx* c) {
     if (c->mom) return LBM_OK;
-    HIPCHK(c, hipMalloc(&c->mom, (size_t)5 * c->N * sizeof(double)));
+    HIPCHK(c, dmalloc(c->stream, (void**)&c->mom, (size_t)5 * c->N * sizeof(double)));
     return LBM_OK;
 }
 
@@ -652,7 +708,7 @@ struct PopFn {
     static lbm_status run(lbm_ctx* c, double* host, bool set) {
         double* dbuf = nullptr;
         const size_t bytes = (size_t)Q * c->N * sizeof(double);
-        HIPCHK(c, hipMalloc(&dbuf, bytes));
+        HIPCHK(c, dmalloc(c->stream, (void**)&dbuf, bytes));
         const Launch L = node_launch(c);
         hipError_t e = hipSuccess;
         if (set) {
@@ -669,8 +725,8 @@ struct PopFn {
             e = hipGetLastError();
             if (e == hipSuccess) e = hipMemcpyAsync(host, dbuf, bytes, hipMemcpyDeviceToHost, c->stream);
         }
+        dfree(c->stream, dbuf);
         hipError_t e2 = hipStreamSynchronize(c->stream);
-        (void)hipFree(dbuf);
         if (e != hipSuccess || e2 != hipSuccess)
             return fail(c, LBM_EDEVICE, "population transfer failed: %s",
                         hipGetErrorString(e != hipSuccess ? e : e2));
@@ -732,3 +788,183 @@ extern "C" lbm_status lbm_moments(lbm_ctx* c, double* rho, double* u, double* p,
     if (st != LBM_OK) return st;
     return poll_health(c, true);
 }
+
+// ---------------------------------------------------------------------------------------
+// Batched stepping of many contexts: one launch per step over every member's tiles
+// (k_step_fused_batch), steps_per_launch launches captured once into a HIP graph.
+constexpr int kBatchTX = 64, kBatchTY = 4, kBatchZC = 16;
+
+struct lbm_batch {
+    std::vector<lbm_ctx*> ctx;
+    int steps_per_launch = 2;
+    int storage = LBM_FP32;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void* table[2] = {nullptr, nullptr};  // device DomainDesc arrays: even / odd steps
+    std::vector<char> host_table[2];      // their sources (alive until the copies are done)
+    bool ran = false;
+    long long blocks = 0;
+    int geom = GEOM_WALLS;                // GEOM_MASK if any member has a cylinder
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    std::vector<hipEvent_t> ready;
+};
+
+static std::string g_batch_error;
+static lbm_status batch_fail(lbm_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_batch_error = buf;
+    return s;
+}
+#define BCHK(call) do { hipError_t e_ = (call); if (e_ != hipSuccess)                        \
+    return batch_fail(e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "%s failed: %s",  \
+                      #call, hipGetErrorString(e_)); } while (0)
+
+template <typename T>
+static lbm_status build_tables(lbm_batch* b) {
+    using R = typename Arith<T>::type;
+    std::vector<DomainDesc<T>> t[2];
+    long long block0 = 0;
+    for (lbm_ctx* c : b->ctx) {
+        const int ntx = (c->p.nx + kBatchTX - 1) / kBatchTX, nty = (c->p.ny + kBatchTY - 1) / kBatchTY;
+        const int zc = std::min(kBatchZC, c->p.nz);
+        const long long nb = (long long)ntx * nty * ((c->p.nz + zc - 1) / zc);
+        const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
+                                                             ? (const void*)&c->pd : (const void*)&c->pf);
+        for (int par = 0; par < 2; ++par) {
+            DomainDesc<T> d{};
+            d.fin = (const T*)c->f[(c->cur + par) & 1];
+            d.fout = (T*)c->f[(c->cur + par + 1) & 1];
+            d.solid = c->solid;
+            d.g = grid_of(c);
+            d.P = P;
+            d.ntx = ntx; d.nty = nty; d.zc = zc; d.block0 = (int)block0;
+            t[par].push_back(d);
+        }
+        block0 += nb;
+    }
+    if (block0 > 0x7fffffffLL) return batch_fail(LBM_EINVAL, "batch too large");
+    b->blocks = block0;
+    const size_t bytes = t[0].size() * sizeof(DomainDesc<T>);
+    for (int par = 0; par < 2; ++par) {
+        b->host_table[par].resize(bytes);
+        std::memcpy(b->host_table[par].data(), t[par].data(), bytes);
+        BCHK(dmalloc(b->stream, &b->table[par], bytes));
+        BCHK(hipMemcpyAsync(b->table[par], b->host_table[par].data(), bytes, hipMemcpyHostToDevice,
+                            b->stream));
+    }
+    // capture steps_per_launch launches, alternating the two tables, on a private stream
+    hipStream_t cap = nullptr;
+    BCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipError_t ce = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (ce != hipSuccess) { (void)hipStreamDestroy(cap); BCHK(ce); }
+    for (int s = 0; s < b->steps_per_launch; ++s) {
+        const DomainDesc<T>* tb = (const DomainDesc<T>*)b->table[s & 1];
+        if (b->geom == GEOM_MASK)
+            hipLaunchKernelGGL((k_step_fused_batch<19, T, GEOM_MASK, kBatchTX, kBatchTY>),
+                               dim3((unsigned)b->blocks), dim3(kBatchTX * kBatchTY), 0, cap,
+                               tb, (int)b->ctx.size());
+        else
+            hipLaunchKernelGGL((k_step_fused_batch<19, T, GEOM_WALLS, kBatchTX, kBatchTY>),
+                               dim3((unsigned)b->blocks), dim3(kBatchTX * kBatchTY), 0, cap,
+                               tb, (int)b->ctx.size());
+    }
+    ce = hipStreamEndCapture(cap, &b->graph);
+    (void)hipStreamDestroy(cap);
+    BCHK(ce);
+    BCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return LBM_OK;
+}
+
+static void batch_free(lbm_batch* b) {
+    if (!b) return;
+    // wait for this batch's own replays only (work queued after them keeps running)
+    if (b->ran && b->done) (void)hipEventSynchronize(b->done);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->stream)
+        for (void* t : b->table) dfree(b->stream, t);
+    if (b->done) (void)hipEventDestroy(b->done);
+    for (hipEvent_t e : b->ready) if (e) (void)hipEventDestroy(e);
+    if (b->own_stream && b->stream) {
+        (void)hipStreamSynchronize(b->stream);
+        (void)hipStreamDestroy(b->stream);
+    }
+}
+
+extern "C" lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, int32_t steps_per_launch,
+                                       void* stream, lbm_batch** out) {
+    if (!ctxs || !out || n < 1) return batch_fail(LBM_EINVAL, "need at least one context");
+    if (steps_per_launch < 2 || steps_per_launch % 2)
+        return batch_fail(LBM_EINVAL, "steps_per_launch must be even and >= 2");
+    *out = nullptr;
+    const int storage = ctxs[0]->p.storage;
+    for (int i = 0; i < n; ++i) {
+        const lbm_ctx* c = ctxs[i];
+        if (!c) return batch_fail(LBM_EINVAL, "null context");
+        if (c->Q != 19) return batch_fail(LBM_EINVAL, "batched stepping supports D3Q19");
+        if (c->p.storage != storage || storage == LBM_FP16)
+            return batch_fail(LBM_EINVAL, "members must share FP32 or FP64 storage");
+        if (!c->initialised || c->failed) return batch_fail(LBM_ESTATE, "member %d not initialised or failed", i);
+        if ((double)c->Q * (double)c->stride * (double)c->elem >= 4294967296.0)
+            return batch_fail(LBM_EINVAL, "member %d has a population buffer of 4 GiB or more", i);
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == c) return batch_fail(LBM_EINVAL, "context %d appears twice", i);
+    }
+    lbm_batch* b = new (std::nothrow) lbm_batch();
+    if (!b) return batch_fail(LBM_ENOMEM, "host allocation failed");
+    b->ctx.assign(ctxs, ctxs + n);
+    b->steps_per_launch = steps_per_launch;
+    b->storage = storage;
+    for (int i = 0; i < n; ++i)
+        if (ctxs[i]->p.cylinder && ctxs[i]->any_solid) b->geom = GEOM_MASK;
+    auto bail = [&](lbm_status s) { batch_free(b); delete b; return s; };
+    hipError_t e = hipSetDevice(ctxs[0]->device);
+    if (e == hipSuccess) {
+        if (stream) b->stream = (hipStream_t)stream;
+        else { e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking); b->own_stream = true; }
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+    b->ready.assign(n, nullptr);
+    for (int i = 0; e == hipSuccess && i < n; ++i) e = hipEventCreateWithFlags(&b->ready[i], hipEventDisableTiming);
+    if (e != hipSuccess) { batch_fail(LBM_EDEVICE, "batch setup failed: %s", hipGetErrorString(e)); return bail(LBM_EDEVICE); }
+    lbm_status st = storage == LBM_FP64 ? build_tables<double>(b) : build_tables<float>(b);
+    if (st != LBM_OK) return bail(st);
+    *out = b;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_run(lbm_batch* b, int64_t nlaunch) {
+    if (!b) return batch_fail(LBM_EINVAL, "null batch");
+    if (nlaunch < 0) return batch_fail(LBM_EINVAL, "nlaunch must be >= 0");
+    for (lbm_ctx* c : b->ctx)
+        if (c->failed) return batch_fail(LBM_ESTATE, "a member failed its health check");
+    BCHK(hipSetDevice(b->ctx[0]->device));
+    // order after each member's stream, replay, then order each member's stream after us
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+        BCHK(hipEventRecord(b->ready[i], b->ctx[i]->stream));
+        BCHK(hipStreamWaitEvent(b->stream, b->ready[i], 0));
+    }
+    for (int64_t k = 0; k < nlaunch; ++k) BCHK(hipGraphLaunch(b->exec, b->stream));
+    BCHK(hipEventRecord(b->done, b->stream));
+    b->ran = true;
+    for (lbm_ctx* c : b->ctx) {
+        BCHK(hipStreamWaitEvent(c->stream, b->done, 0));
+        c->steps += nlaunch * b->steps_per_launch;      // even count: c->cur unchanged
+    }
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_destroy(lbm_batch* b) {
+    if (!b) return LBM_OK;
+    batch_free(b);
+    delete b;
+    return LBM_OK;
+}
+
+extern "C" const char* lbm_batch_last_error(void) { return g_batch_error.c_str(); }

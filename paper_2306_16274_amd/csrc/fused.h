@@ -7,14 +7,13 @@
 //
 //   * a workgroup owns a TX x TY tile of (x, y) columns and marches along z over a chunk
 //     of planes [z0, z1); thread (lx, ly) owns column (x0+lx, y0+ly);
-//   * psi of the planes z-1, z, z+1, z+2 lives in an LDS ring of four planes (tile plus
-//     halo); one barrier per plane;
-//   * software pipeline: at plane z a thread first issues the loads of its own node two
-//     planes ahead (z+2), then collides plane z from registers (loaded one iteration
-//     earlier) with psi(z-1..z+1) from LDS and stores it, and only then sums the
-//     z+2 populations into psi. The loads are in flight while the collision runs;
-//   * the first H = 2(TX+TY)+4 threads also pull the populations of the halo nodes of
-//     plane z+2, only to form their psi. Those rows are pulled by the neighbouring tiles
+//   * psi of the planes around z lives in an LDS ring of four planes (tile plus halo);
+//     one barrier per plane. At plane z a thread pulls the populations of its own node
+//     of plane z+1 into registers and writes its psi, then (after the barrier) collides
+//     plane z from the registers filled one iteration earlier, with psi(z-1..z+1) from
+//     LDS, and stores it;
+//   * the first H threads also pull the populations of the halo nodes of plane z+1,
+//     only to form their psi (H = 2(TX+TY)+4 for a tile, 2 TX for full rows). Those rows are pulled by the neighbouring tiles
 //     at about the same time: tiles are mapped to XCDs in contiguous ranges (workgroup b
 //     runs on XCD b mod 8), so neighbouring tiles share an L2 and the halo re-reads stay
 //     on chip;
@@ -47,25 +46,58 @@ __device__ __forceinline__ void st_off(T* __restrict__ base, unsigned byte_off, 
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
+// How a kernel learns which nodes are solid: none (fully periodic), wall layers only
+// (decided from the coordinates, no memory traffic), or the byte mask (cylinder).
+enum { GEOM_NONE = 0, GEOM_WALLS = 1, GEOM_MASK = 2 };
+
+// Wall solidity of the coordinates c-1, c, c+1 (wrapped) along one axis, as bits 0..2.
+__device__ __forceinline__ unsigned wall_bits(int c, int n, int walls, int axis) {
+    const bool lo = (walls >> (2 * axis)) & 1, hi = (walls >> (2 * axis + 1)) & 1;
+    unsigned b = 0;
+#pragma unroll
+    for (int d = -1; d <= 1; ++d) {
+        int cc = c + d;
+        cc = cc < 0 ? cc + n : (cc >= n ? cc - n : cc);
+        if ((lo && cc == 0) || (hi && cc == n - 1)) b |= 1u << (d + 1);
+    }
+    return b;
+}
+struct WallBits { unsigned wx, wy, wz; };
+
 // Element index of the pull source x - e_i of population i for a column whose 3x3
 // in-plane neighbour indices are xy[(dy+1)*3 + dx+1] and whose plane indices are
 // zo[dz+1]; with bounce-back from the node itself when the source is solid.
-template <int Q, bool SOLID>
+template <int Q, int GEOM>
 __device__ __forceinline__ void pull_source(int i, const int* xy, const int* zo,
-                                            const uint8_t* __restrict__ solid, int& e, int& pop) {
-    e = xy[(1 - vel_y(i)) * 3 + (1 - vel_x(i))] + zo[1 - vel_z(i)];
+                                            const uint8_t* __restrict__ solid,
+                                            const WallBits& wb, int& e, int& pop) {
+    const int ex = vel_x(i), ey = vel_y(i), ez = vel_z(i);
+    e = xy[(1 - ey) * 3 + (1 - ex)] + zo[1 - ez];
     pop = i;
-    if (SOLID && i != 0 && solid[e]) { e = xy[4] + zo[1]; pop = opposite(i); }
+    bool s = false;
+    if (GEOM == GEOM_MASK && i != 0) s = solid[e];
+    if (GEOM == GEOM_WALLS && i != 0)
+        s = ((wb.wx >> (1 - ex)) | (wb.wy >> (1 - ey)) | (wb.wz >> (1 - ez))) & 1u;
+    if (s) { e = xy[4] + zo[1]; pop = opposite(i); }
+}
+
+template <int GEOM>
+__device__ __forceinline__ bool node_solid(const uint8_t* __restrict__ solid, int n,
+                                           const WallBits& wb) {
+    if (GEOM == GEOM_MASK) return solid[n] != 0;
+    if (GEOM == GEOM_WALLS) return ((wb.wx | wb.wy | wb.wz) >> 1) & 1u;
+    return false;
 }
 
 // Issue the Q loads of a column's node (values land in v[]).
-template <int Q, typename T, typename R, bool SOLID>
+template <int Q, typename T, typename R, int GEOM>
 __device__ __forceinline__ void pull_loads(const T* __restrict__ f, const uint8_t* __restrict__ solid,
-                                           const int* xy, const int* zo, unsigned pst, R* v) {
+                                           const int* xy, const int* zo, const WallBits& wb,
+                                           unsigned pst, R* v) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         int e, pop;
-        pull_source<Q, SOLID>(i, xy, zo, solid, e, pop);
+        pull_source<Q, GEOM>(i, xy, zo, solid, wb, e, pop);
         v[i] = static_cast<R>(ld_off(f, (unsigned)e * (unsigned)sizeof(T) + (unsigned)pop * pst));
     }
 }
@@ -80,15 +112,14 @@ __device__ __forceinline__ R sum_q(const R* v) {
 
 // FULLX: the tile spans the whole x extent (TX == nx); x wraps inside the tile and the
 // halo is just the rows y0-1 and y0+TY (H = 2 TX, one halo node per thread when TY = 2).
-// PIPE: prefetch the own node two planes ahead (three register sets) so that its loads
-// overlap the collision of the current plane.
-// REMAP: map workgroups to tiles so that each XCD gets a contiguous tile range.
-template <int Q, typename T, bool SOLID, int TX, int TY, bool FULLX, bool PIPE>
-__global__ __launch_bounds__(TX * TY) void k_step_fused(const T* __restrict__ fin,
-                                                       T* __restrict__ fout,
-                                                       const uint8_t* __restrict__ solid,
-                                                       Grid g, Phys<typename Arith<T>::type> P,
-                                                       int ntx, int nty, int zc, int remap) {
+// One tile (workgroup) of the fused step: tile index t of a domain with ntx x nty tiles
+// per plane and z-chunks of zc planes. Shared by the single-domain kernel and the
+// multi-domain (batched) kernel.
+template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX>
+__device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restrict__ fout,
+                                           const uint8_t* __restrict__ solid, const Grid& g,
+                                           const Phys<typename Arith<T>::type>& P,
+                                           int t, int ntx, int nty, int zc) {
     using R = typename Arith<T>::type;
     constexpr int LX = FULLX ? TX : TX + 2, LY = TY + 2;
     constexpr int OX = FULLX ? 0 : 1;                 // LDS column of tile column 0
@@ -96,7 +127,6 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(const T* __restrict__ fi
     static_assert(H <= TX * TY, "halo larger than the workgroup");
     __shared__ R ring[4][LY][LX];
 
-    int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int ix = t % ntx; t /= ntx;
     const int iy = t % nty;
     const int iz = t / nty;
@@ -135,17 +165,29 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(const T* __restrict__ fi
         zo[1] = wrapc(zp, g.nz) * nxy;
         zo[2] = wrapc(zp + 1, g.nz) * nxy;
     };
+    // wall solidity of the own and the halo column (x, y fixed; z per plane)
+    WallBits wo{0u, 0u, 0u}, wh{0u, 0u, 0u};
+    if (GEOM == GEOM_WALLS) {
+        wo.wx = wall_bits(wrapc(x, g.nx), g.nx, g.walls, 0);
+        wo.wy = wall_bits(wrapc(y, g.ny), g.ny, g.walls, 1);
+        wh.wx = wall_bits(wrapc(x0 + hx, g.nx), g.nx, g.walls, 0);
+        wh.wy = wall_bits(wrapc(y0 + hy, g.ny), g.ny, g.walls, 1);
+    }
+    auto zbits = [&](int zp) {
+        return GEOM == GEOM_WALLS ? wall_bits(wrapc(zp, g.nz), g.nz, g.walls, 2) : 0u;
+    };
     auto psi_of = [&](R drho) { return pseudopotential<R>(P.rho_ref + drho, P); };
     // psi of the halo node of plane zp into ring slot
     auto halo_psi = [&](int zp, int slot) {
         if (!has_halo) return;
         int zo[3];
         zoffs(zp, zo);
+        const WallBits wb{wh.wx, wh.wy, zbits(zp)};
         R hv;
-        if (SOLID && solid[hxy[4] + zo[1]]) hv = R(-1);
+        if (node_solid<GEOM>(solid, hxy[4] + zo[1], wb)) hv = R(-1);
         else {
             R v[Q];
-            pull_loads<Q, T, R, SOLID>(fin, solid, hxy, zo, pst, v);
+            pull_loads<Q, T, R, GEOM>(fin, solid, hxy, zo, wb, pst, v);
             hv = psi_of(sum_q<Q, R>(v));
         }
         ring[slot][hy + 1][hx + OX] = hv;
@@ -154,8 +196,9 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(const T* __restrict__ fi
     auto own_psi = [&](int zp, int slot, R* v) {
         int zo[3];
         zoffs(zp, zo);
-        const bool s = SOLID && solid[oxy[4] + zo[1]];
-        pull_loads<Q, T, R, SOLID>(fin, solid, oxy, zo, pst, v);
+        const WallBits wb{wo.wx, wo.wy, zbits(zp)};
+        const bool s = node_solid<GEOM>(solid, oxy[4] + zo[1], wb);
+        pull_loads<Q, T, R, GEOM>(fin, solid, oxy, zo, wb, pst, v);
         ring[slot][ly + 1][lx + OX] = s ? R(-1) : psi_of(sum_q<Q, R>(v));
     };
     // LDS column of tile column lx + dx
@@ -182,48 +225,60 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(const T* __restrict__ fi
         }
     };
 
-    if (PIPE) {
-        R c0[Q], c1[Q], c2[Q];
-        own_psi(z0 - 1, 0, c2);
-        halo_psi(z0 - 1, 0);
-        own_psi(z0, 1, c0);
-        halo_psi(z0, 1);
-        own_psi(z0 + 1, 2, c1);
-        halo_psi(z0 + 1, 2);
+    R cur[Q], nxt[Q];
+    own_psi(z0 - 1, 0, nxt);
+    halo_psi(z0 - 1, 0);
+    own_psi(z0, 1, cur);
+    halo_psi(z0, 1);
+    for (int z = z0; z < z1; ++z) {
+        const int k = z - z0;
+        own_psi(z + 1, (k + 2) & 3, nxt);
+        halo_psi(z + 1, (k + 2) & 3);
         __syncthreads();
-        for (int z = z0; z < z1; ++z) {
-            const int k = z - z0;
-            const bool more = z + 1 < z1;        // plane z+1 is collided next: psi(z+2) needed
-            int zo2[3];
-            zoffs(z + 2, zo2);
-            if (more) pull_loads<Q, T, R, SOLID>(fin, solid, oxy, zo2, pst, c2);
-            collide_store(c0, z, k & 3, (k + 1) & 3, (k + 2) & 3);
-            if (more) {
-                const int s3 = (k + 3) & 3;
-                const bool s = SOLID && solid[oxy[4] + zo2[1]];
-                ring[s3][ly + 1][lx + OX] = s ? R(-1) : psi_of(sum_q<Q, R>(c2));
-                halo_psi(z + 2, s3);
-            }
-            __syncthreads();
+        collide_store(cur, z, k & 3, (k + 1) & 3, (k + 2) & 3);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) { c0[i] = c1[i]; c1[i] = c2[i]; }
-        }
-    } else {
-        R cur[Q], nxt[Q];
-        own_psi(z0 - 1, 0, nxt);
-        halo_psi(z0 - 1, 0);
-        own_psi(z0, 1, cur);
-        halo_psi(z0, 1);
-        for (int z = z0; z < z1; ++z) {
-            const int k = z - z0;
-            own_psi(z + 1, (k + 2) & 3, nxt);
-            halo_psi(z + 1, (k + 2) & 3);
-            __syncthreads();
-            collide_store(cur, z, k & 3, (k + 1) & 3, (k + 2) & 3);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
-        }
+        for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
     }
+}
+
+// Single domain. remap != 0: map workgroups to tiles so that each XCD gets a contiguous
+// tile range (workgroup b runs on XCD b mod 8).
+template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX>
+__global__ __launch_bounds__(TX * TY) void k_step_fused(const T* __restrict__ fin,
+                                                       T* __restrict__ fout,
+                                                       const uint8_t* __restrict__ solid,
+                                                       Grid g, Phys<typename Arith<T>::type> P,
+                                                       int ntx, int nty, int zc, int remap) {
+    const int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    fused_tile<Q, T, GEOM, TX, TY, FULLX>(fin, fout, solid, g, P, t, ntx, nty, zc);
+}
+
+// One domain of a batched step: its buffers, geometry, physics and the first workgroup
+// of the batched grid that works on it.
+template <typename T>
+struct DomainDesc {
+    const T* fin;
+    T* fout;
+    const uint8_t* solid;
+    Grid g;
+    Phys<typename Arith<T>::type> P;
+    int ntx, nty, zc, block0;
+};
+
+// Many independent lattices advanced by one launch: workgroup b belongs to the last
+// domain whose block0 <= b (binary search over the table, uniform per workgroup).
+template <int Q, typename T, int GEOM, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void k_step_fused_batch(const DomainDesc<T>* __restrict__ d,
+                                                             int ndom) {
+    const int b = blockIdx.x;
+    int lo = 0, hi = ndom - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].block0 <= b) lo = mid; else hi = mid - 1;
+    }
+    const DomainDesc<T>& D = d[lo];
+    fused_tile<Q, T, GEOM, TX, TY, false>(D.fin, D.fout, D.solid, D.g, D.P, b - D.block0,
+                                                D.ntx, D.nty, D.zc);
 }
 
 }  // namespace lbmk

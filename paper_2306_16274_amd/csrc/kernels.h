@@ -23,6 +23,7 @@ __device__ __forceinline__ void store_as(T* p, R v) { *p = static_cast<T>(v); }
 
 struct Grid {
     int nx, ny, nz;
+    int walls;                // solid layers: bit 2a = axis a low face, bit 2a+1 = high face
     long long stride;         // elements between population planes
 };
 
@@ -362,6 +363,27 @@ __global__ __launch_bounds__(256) void k_health_final(const double* __restrict__
         __syncthreads();
     }
     if (threadIdx.x == 0) { out[0] = red[0][0]; out[1] = red[1][0]; }
+}
+
+// Solid mask: wall layers on the faces set in g.walls and nodes whose centre lies in the
+// x-aligned cylinder (y - cy)^2 + (z - cz)^2 <= r^2 (float64, as on the host).
+__global__ __launch_bounds__(256) void k_build_solid(uint8_t* __restrict__ solid, Grid g, int cylinder,
+                                                     double cy, double cz, double r) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    const int c[3] = {x, y, z}, n[3] = {g.nx, g.ny, g.nz};
+    bool s = false;
+    for (int a = 0; a < 3; ++a) {
+        if (((g.walls >> (2 * a)) & 1) && c[a] == 0) s = true;
+        if (((g.walls >> (2 * a + 1)) & 1) && c[a] == n[a] - 1) s = true;
+    }
+    if (cylinder) {
+        const double dy = y - cy, dz = z - cz;
+        if (dy * dy + dz * dz <= r * r) s = true;
+    }
+    solid[x + (long long)g.nx * (y + (long long)g.ny * z)] = s ? 1 : 0;
 }
 
 }  // namespace lbmk

@@ -80,6 +80,10 @@ _SIGS = {
     "lbm_coexistence": (ctypes.c_int, [ctypes.POINTER(lbm_params), ctypes.POINTER(_D),
                                        ctypes.POINTER(_D)]),
     "lbm_footprint_bytes": (ctypes.c_int64, [ctypes.POINTER(lbm_params)]),
+    "lbm_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+    "lbm_batch_run": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "lbm_batch_destroy": (ctypes.c_int, [_P]),
+    "lbm_batch_last_error": (ctypes.c_char_p, []),
 }
 
 
@@ -201,6 +205,34 @@ def lbm_coexistence(params):
 
 def lbm_footprint_bytes(params):
     return library().lbm_footprint_bytes(ctypes.byref(params))
+
+
+def _check_batch(status):
+    if status != LBM_OK:
+        msg = library().lbm_batch_last_error()
+        raise LbmError(status, msg.decode() if msg else "")
+
+
+def lbm_batch_create(ctxs, steps_per_launch, stream=None):
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value if isinstance(c, ctypes.c_void_p) else c
+                                          for c in ctxs])
+    out = ctypes.c_void_p()
+    _check_batch(library().lbm_batch_create(ctypes.cast(arr, _P), len(ctxs),
+                                            int(steps_per_launch), stream, ctypes.byref(out)))
+    return out
+
+
+def lbm_batch_run(batch, nlaunch):
+    _check_batch(library().lbm_batch_run(batch, int(nlaunch)))
+
+
+def lbm_batch_destroy(batch):
+    _check_batch(library().lbm_batch_destroy(batch))
+
+
+def lbm_batch_last_error():
+    msg = library().lbm_batch_last_error()
+    return msg.decode() if msg else ""
 
 
 class Lattice:
