@@ -24,8 +24,10 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak, GB/s
 
 
 def kernel_source_hash():
+    """Hash of the fused step kernel's code and launch configuration (the files it is
+    compiled from); a counter summary taken on other sources is not used."""
     h = hashlib.sha256()
-    for name in ("lattice.h", "kernels.h", "fused.h", "api.hip"):
+    for name in ("lattice.h", "common.h", "fused.h"):
         with open(os.path.join(ROOT, "paper_2306_16274_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

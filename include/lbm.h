@@ -143,6 +143,21 @@ int64_t lbm_steps_done(const lbm_ctx* c);
    read 0. Synchronous.                                                                 */
 lbm_status lbm_moments(lbm_ctx* c, double* rho, double* u, double* p, double* totals);
 
+/* Liquid-phase diagnostics of the current state, reduced on the device: the spreading
+   diameter of the film on a wall (Sec. IV A, from the liquid area of the first fluid
+   layer), the contact time (Sec. IV B, the droplet has left the solid when no liquid node
+   touches it) and the liquid volume (Sec. IV B). A fluid node is liquid when rho > threshold,
+   with rho formed and compared in float64 exactly as lbm_moments returns it.
+     count_z  NULL or nz int64: liquid nodes in each z plane (index k = plane z = k);
+     wetted   NULL or one int64: liquid nodes with at least one solid neighbour among the
+              lattice velocities;
+     volume   NULL or one double: sum over fluid nodes of clamp((rho - rho_v)/(rho_l - rho_v),
+              0, 1), a fixed-order float64 sum.
+   Errors: LBM_EINVAL unless rho_l > rho_v and all three are finite; LBM_ESTATE before
+   initialisation. Synchronous.                                                          */
+lbm_status lbm_liquid_stats(lbm_ctx* c, double threshold, double rho_v, double rho_l,
+                            int64_t* count_z, int64_t* wetted, double* volume);
+
 /* Measurement aid: run nsteps time steps (as lbm_step) with a HIP event pair around every
    kernel launch on the context stream, waiting after each step. avg_ms[k] receives the
    mean duration in ms of the k-th kernel of a step and names[k] (if names != NULL) its

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm_hip.so")
 SOURCES = ["api.hip"]
-HEADERS = ["lattice.h", "kernels.h", "../../include/lbm.h"]
+HEADERS = ["lattice.h", "common.h", "kernels.h", "fused.h", "../../include/lbm.h"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -14,6 +14,7 @@
 
 #include "../../include/lbm.h"
 #include "fused.h"
+#include "kernels.h"
 
 using namespace lbmk;
 
@@ -471,9 +472,6 @@ static const char* const kFusedNames[] = {"k_step_fused"};
 
 // Tile configurations of the fused kernel. 256 x 2 full rows: the x-shifted pulls of a
 // row stay inside one workgroup and the halo is two rows; 32 x 8 tiles for other widths.
-struct FusedCfg { int tx, ty; bool fullx; };
-static const FusedCfg kFusedCfgs[] = {{32, 8, false}, {256, 2, true}, {256, 4, true}};
-constexpr int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
 
 static int default_fused_cfg(const lbm_ctx* c) {
     if (const char* e = getenv("LBM_FUSED_CONFIG")) {      // tuning override
@@ -481,8 +479,7 @@ static int default_fused_cfg(const lbm_ctx* c) {
         if (v >= 0 && v < kNumFusedCfgs && (!kFusedCfgs[v].fullx || c->p.nx == kFusedCfgs[v].tx))
             return v;
     }
-    if (c->p.nx == 256) return c->p.storage == LBM_FP64 ? 1 : 2;   // 256x4 needs <= 128 VGPRs
-    return 0;
+    return default_fused_cfg_index(c->p.nx, c->p.storage == LBM_FP64);
 }
 
 // Planes per z-chunk and tile order. Full-row tiles: 64-plane chunks (about one
@@ -491,7 +488,7 @@ static int default_fused_cfg(const lbm_ctx* c) {
 // MI355X at 256^3 (D3Q19, FP32 and FP64).
 static void fused_chunking(const lbm_ctx* c, int& zc, int& remap) {
     const bool fullx = kFusedCfgs[c->fused_cfg].fullx;
-    zc = fullx ? 64 : 16;
+    zc = fullx ? kFusedZcFullRow : kFusedZcTiled;
     remap = fullx ? 0 : 1;
     if (const char* e = getenv("LBM_FUSED_ZC")) zc = std::max(1, atoi(e));      // tuning override
     if (const char* e = getenv("LBM_FUSED_REMAP")) remap = atoi(e) != 0;       // tuning override
@@ -767,7 +764,7 @@ struct MomentsFn {
         hipLaunchKernelGGL((k_moments<Q, T>), L.grid, L.block, 0, c->stream,
                            (const T*)c->f[c->cur], (const R*)c->psi, drho, du, dp, c->partial,
                            grid_of(c), P);
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, c->stream, c->partial,
+        hipLaunchKernelGGL(k_sum_rows<5>, dim3(1), dim3(256), 0, c->stream, c->partial,
                            nblocks(L), c->dtot);
         HIPCHK(c, hipGetLastError());
         const size_t nb = c->N * sizeof(double);
@@ -785,6 +782,52 @@ extern "C" lbm_status lbm_moments(lbm_ctx* c, double* rho, double* u, double* p,
     if (!c->initialised) return fail(c, LBM_ESTATE, "populations not initialised");
     HIPCHK(c, hipSetDevice(c->device));
     lbm_status st = dispatch<MomentsFn>(c, rho, u, p, totals);
+    if (st != LBM_OK) return st;
+    return poll_health(c, true);
+}
+
+template <int Q, typename T>
+struct LiquidFn {
+    static lbm_status run(lbm_ctx* c, double threshold, double rho_v, double rho_l,
+                          int64_t* count_z, int64_t* wetted, double* volume) {
+        using R = typename Arith<T>::type;
+        const Launch L = node_launch(c);
+        const long long nb = nblocks(L), nz = c->p.nz;
+        const long long per_plane = (long long)L.grid.x * L.grid.y;   // blocks of one z plane
+        lbm_status st = ensure_partial(c, 3 * nb + 3 * nz + 3);
+        if (st != LBM_OK) return st;
+        double* plane = c->partial + 3 * nb;       // nz rows: liquid, wetted, volume
+        double* tot = plane + 3 * nz;
+        const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
+                                                             ? (const void*)&c->pd : (const void*)&c->pf);
+        launch_psi<Q, T>(c, c->f[c->cur]);
+        hipLaunchKernelGGL((k_liquid_stats<Q, T>), L.grid, L.block, 0, c->stream,
+                           (const T*)c->f[c->cur], (const R*)c->psi, c->partial, grid_of(c),
+                           P.rho_ref, threshold, rho_v, rho_l);
+        hipLaunchKernelGGL(k_sum_rows<3>, dim3((unsigned)nz), dim3(256), 0, c->stream,
+                           c->partial, per_plane, plane);
+        hipLaunchKernelGGL(k_sum_rows<3>, dim3(1), dim3(256), 0, c->stream, plane, nz, tot);
+        HIPCHK(c, hipGetLastError());
+        std::vector<double> h((size_t)(3 * nz + 3));
+        HIPCHK(c, hipMemcpyAsync(h.data(), plane, h.size() * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (count_z)
+            for (long long k = 0; k < nz; ++k) count_z[k] = (int64_t)h[(size_t)(3 * k)];
+        if (wetted) *wetted = (int64_t)h[(size_t)(3 * nz + 1)];
+        if (volume) *volume = h[(size_t)(3 * nz + 2)];
+        return LBM_OK;
+    }
+};
+
+extern "C" lbm_status lbm_liquid_stats(lbm_ctx* c, double threshold, double rho_v, double rho_l,
+                                       int64_t* count_z, int64_t* wetted, double* volume) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    if (!c->initialised) return fail(c, LBM_ESTATE, "populations not initialised");
+    if (!(rho_l > rho_v) || !std::isfinite(rho_l) || !std::isfinite(rho_v) || !std::isfinite(threshold))
+        return fail(c, LBM_EINVAL, "need finite threshold and rho_l > rho_v");
+    HIPCHK(c, hipSetDevice(c->device));
+    lbm_status st = dispatch<LiquidFn>(c, threshold, rho_v, rho_l, count_z, wetted, volume);
     if (st != LBM_OK) return st;
     return poll_health(c, true);
 }

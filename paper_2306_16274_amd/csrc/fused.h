@@ -26,9 +26,23 @@
 // outside the domain compute psi of the wrapped node but never store.
 #pragma once
 
-#include "kernels.h"
+#include "common.h"
 
 namespace lbmk {
+
+// Launch configurations of k_step_fused: tile width and height, and whether the tile spans
+// the whole x row (then nx must equal tx). Defaults (from a sweep at 256^3 on MI355X):
+// full-row 256x4 tiles for 4-byte storage, 256x2 for FP64 (256x4 in FP64 needs more than 128
+// VGPRs and spills), 32x8 tiles for other widths. Full-row tiles march through 64-plane
+// z-chunks in dispatch order; small tiles through 16-plane chunks in XCD-contiguous order.
+struct FusedCfg { int tx, ty; bool fullx; };
+constexpr FusedCfg kFusedCfgs[] = {{32, 8, false}, {256, 2, true}, {256, 4, true}};
+constexpr int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
+constexpr int kFusedZcFullRow = 64, kFusedZcTiled = 16;
+
+constexpr int default_fused_cfg_index(int nx, bool fp64) {
+    return nx == 256 ? (fp64 ? 1 : 2) : 0;
+}
 
 // Workgroup b -> tile index such that each XCD (b mod 8) gets a contiguous tile range.
 __device__ __forceinline__ int xcd_tile(int b, int nb) {

@@ -1,60 +1,14 @@
-// HIP kernels of the time step (gfx950). Population storage is SoA: plane i of the
-// buffer holds population i of every node (index n = x + nx (y + ny z)), planes `stride`
-// elements apart. The stored state is the post-collision f_bar* of the previous step; a
-// step pulls f_bar_i(x) = f_bar*_i(x - e_i) (Eq. (9) read backwards), or, when x - e_i is
-// solid, the halfway bounce-back value f_bar*_opp(i)(x).
+// HIP kernels of the two-pass time step, the diagnostics and the initialisation (gfx950).
+// Storage layout and the pull convention: common.h.
 //
 // Two-pass step:
 //   k_density_psi  gather -> rho -> psi(rho); psi < 0 marks solid nodes
 //   k_collide      gather + psi of the 26-neighbourhood -> forces -> collision -> store
 #pragma once
 
-#include "lattice.h"
+#include "common.h"
 
 namespace lbmk {
-
-template <typename T> struct Arith { using type = float; };
-template <> struct Arith<double> { using type = double; };
-
-template <typename T, typename R>
-__device__ __forceinline__ R load_as(const T* p) { return static_cast<R>(*p); }
-template <typename T, typename R>
-__device__ __forceinline__ void store_as(T* p, R v) { *p = static_cast<T>(v); }
-
-struct Grid {
-    int nx, ny, nz;
-    int walls;                // solid layers: bit 2a = axis a low face, bit 2a+1 = high face
-    long long stride;         // elements between population planes
-};
-
-// Indices of x + e_j for all j (periodic wrap on every axis).
-template <int Q>
-__device__ __forceinline__ void neighbour_index(const Grid& g, int x, int y, int z, int* nb) {
-    const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
-    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
-    const int nxy = g.nx * g.ny;
-    const int ox[3] = {xm, x, xp};
-    const int oy[3] = {ym * g.nx, y * g.nx, yp * g.nx};
-    const int oz[3] = {zm * nxy, z * nxy, zp * nxy};
-#pragma unroll
-    for (int j = 0; j < Q; ++j)
-        nb[j] = ox[vel_x(j) + 1] + oy[vel_y(j) + 1] + oz[vel_z(j) + 1];
-}
-
-// Pull the Q populations of node n, with bounce-back where the source is solid.
-template <int Q, typename T, typename R>
-__device__ __forceinline__ void gather(const T* __restrict__ f, long long stride, int n,
-                                       const int* nb, const bool* solid_nb, R* d) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int o = opposite(i);
-        // source x - e_i = x + e_o
-        const long long idx = solid_nb[o] ? (long long)o * stride + n
-                                          : (long long)i * stride + nb[o];
-        d[i] = load_as<T, R>(f + idx);
-    }
-}
 
 template <int Q, typename T, bool SOLID>
 __global__ __launch_bounds__(256) void k_density_psi(const T* __restrict__ f,
@@ -173,23 +127,6 @@ __global__ __launch_bounds__(256) void k_moments(const T* __restrict__ fin,
         const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
         partial[b * 5 + tid] = s;
     }
-}
-
-// Fixed-order sum of nblocks x 5 partials into out[5] (one block of 256 threads).
-__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial,
-                                                      long long nblocks, double* __restrict__ out) {
-    __shared__ double red[5][256];
-    double acc[5] = {0, 0, 0, 0, 0};
-    for (long long b = threadIdx.x; b < nblocks; b += blockDim.x)
-        for (int c = 0; c < 5; ++c) acc[c] += partial[b * 5 + c];
-    for (int c = 0; c < 5; ++c) red[c][threadIdx.x] = acc[c];
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int c = 0; c < 5; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x < 5) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
 // Store f_bar(x) (float64, Q planes of N) into the pull layout: population i of node x
@@ -363,6 +300,85 @@ __global__ __launch_bounds__(256) void k_health_final(const double* __restrict__
         __syncthreads();
     }
     if (threadIdx.x == 0) { out[0] = red[0][0]; out[1] = red[1][0]; }
+}
+
+// Liquid diagnostics of the current state (Sec. IV A spreading diameter, Sec. IV B
+// contact time and liquid volume). Per block: the number of liquid fluid nodes
+// (rho > threshold), of those the ones with a solid neighbour (in contact with a wall or
+// the cylinder), and the liquid volume fraction sum clamp((rho - rho_v)/(rho_l - rho_v), 0, 1).
+// rho is formed exactly as k_moments forms it (float64 sum of rho_ref and the zeroth
+// moment), so a threshold applied to the density field lbm_moments returns makes the same
+// decisions. Needs psi of the current state (solid marker) from k_density_psi.
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_liquid_stats(const T* __restrict__ fin,
+                                                      const typename Arith<T>::type* __restrict__ psi,
+                                                      double* __restrict__ partial, Grid g,
+                                                      typename Arith<T>::type rho_ref,
+                                                      double threshold, double rho_v, double rho_l) {
+    using R = typename Arith<T>::type;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    double acc[3] = {0, 0, 0};
+    if (x < g.nx && y < g.ny) {
+        const int n = x + g.nx * (y + g.ny * z);
+        if (psi[n] >= R(0)) {
+            int nb[Q];
+            neighbour_index<Q>(g, x, y, z, nb);
+            bool snb[Q];
+            bool touches = false;
+#pragma unroll
+            for (int j = 1; j < Q; ++j) { snb[j] = psi[nb[j]] < R(0); touches |= snb[j]; }
+            snb[0] = false;
+            R d[Q];
+            gather<Q, T, R>(fin, g.stride, n, nb, snb, d);
+            const double rho = (double)rho_ref + (double)forward<Q, R>(d).k000;
+            if (rho > threshold) { acc[0] = 1.0; acc[1] = touches ? 1.0 : 0.0; }
+            acc[2] = fmin(fmax((rho - rho_v) / (rho_l - rho_v), 0.0), 1.0);
+        }
+    }
+    __shared__ double red[3][8];
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double v = acc[c];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) red[c][wave] = v;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        const int nw = (blockDim.x * blockDim.y + 63) / 64;
+        double s = 0;
+        for (int w = 0; w < nw; ++w) s += red[tid][w];
+        const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+        partial[b * 3 + tid] = s;
+    }
+}
+
+// Fixed-order sums of rows of C values: block k adds rows [k rows_per_group, (k+1)
+// rows_per_group) of `in` into out[k C .. k C + C - 1] (one block of 256 threads per group).
+template <int C>
+__global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ in,
+                                                  long long rows_per_group, double* __restrict__ out) {
+    __shared__ double red[C][256];
+    const double* base = in + (long long)blockIdx.x * rows_per_group * C;
+    double acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.0;
+    for (long long r = threadIdx.x; r < rows_per_group; r += blockDim.x)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] += base[r * C + c];
+#pragma unroll
+    for (int c = 0; c < C; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+#pragma unroll
+            for (int c = 0; c < C; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < C) out[(long long)blockIdx.x * C + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // Solid mask: wall layers on the faces set in g.walls and nodes whose centre lies in the

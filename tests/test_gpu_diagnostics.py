@@ -1,0 +1,93 @@
+"""Liquid diagnostics on the device (lbm_liquid_stats) against the oracle and against the
+density field lbm_moments returns."""
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from oracle import lbm as olbm
+from tests.helpers import gpu_params, maxwell, oracle_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2306_16274_amd import lbm
+    lbm.library()
+    return lbm
+
+
+def _sessile(Q):
+    # droplet resting on the z = 0 wall next to a cylinder, ragged sizes (several blocks of
+    # the diagnostic launch in x and y, one partial)
+    return si.Workload("sessile", Q, 70, 37, 23, T_over_Tc=0.7, walls=("z_lo",), G_ads=0.1,
+                       cylinder=(8.0, 6.0, 4.0), R=9.0, centre=(35, 20, 9), nu=0.1,
+                       noise=0.01, seed=5)
+
+
+@pytest.mark.parametrize("Q", [19, 27])
+def test_liquid_stats_fp64_matches_oracle(L, Q):
+    w = _sessile(Q)
+    rv, rl = maxwell(w)
+    thr = 0.5 * (rv + rl)
+    cx, cy, cz = w.droplet_centre()
+    with L.Lattice(gpu_params(w, "fp64")) as lat:
+        lat.init_droplet(cx, cy, cz, w.R, w.W, rl, rv, 0.0, 0.0, 0.0, w.noise, w.seed)
+        lat.step(7)
+        counts, wet, vol = lat.liquid_stats(thr, rv, rl)
+        f = lat.get_populations()
+    P = oracle_params(w)
+    solid = olbm.solid_mask(P)
+    oc, ow, ov = olbm.liquid_stats(f, P, thr, rv, rl, solid)
+    rho = f.sum(0)
+    near = (np.abs(rho - thr) < 1e-12) & ~solid
+    print(f"Q{Q}: liquid {counts.sum()} wetted {wet} volume {vol:.6f}; near-threshold nodes {near.sum()}")
+    assert near.sum() == 0
+    assert np.array_equal(counts, oc)
+    assert wet == ow and wet > 0
+    assert abs(vol - ov) <= 1e-12 * ov
+
+
+@pytest.mark.parametrize("storage,rho_ref", [("fp32", "vapour"), ("fp64", 0.0)])
+def test_liquid_stats_same_decisions_as_moments(L, storage, rho_ref):
+    """Counts equal those from the density field of lbm_moments with the same threshold
+    (the kernel forms rho the same way), bit for bit."""
+    w = _sessile(19)
+    rv, rl = maxwell(w)
+    thr = 0.5 * (rv + rl)
+    ref = rv if rho_ref == "vapour" else rho_ref
+    P = oracle_params(w)
+    solid = olbm.solid_mask(P)
+    touches = np.zeros(solid.shape, dtype=bool)
+    for e in P.lat.e[1:]:
+        touches |= olbm.neighbour(solid, e)
+    cx, cy, cz = w.droplet_centre()
+    with L.Lattice(gpu_params(w, storage, rho_ref=ref)) as lat:
+        lat.init_droplet(cx, cy, cz, w.R, w.W, rl, rv, 0.0, 0.0, -0.01, w.noise, w.seed)
+        for _ in range(3):
+            lat.step(20)
+            counts, wet, vol = lat.liquid_stats(thr, rv, rl)
+            rho = lat.moments(want=("rho",))["rho"]
+            liquid = ~solid & (rho > thr)
+            assert np.array_equal(counts, liquid.sum(axis=(1, 2)))
+            assert wet == int((liquid & touches).sum())
+            v = np.clip((rho - rv) / (rl - rv), 0.0, 1.0)[~solid].sum()
+            assert abs(vol - v) <= 1e-12 * v
+
+
+def test_liquid_stats_rejects_bad_arguments(L):
+    w = _sessile(19)
+    rv, rl = maxwell(w)
+    with L.Lattice(gpu_params(w, "fp32", rho_ref=rv)) as lat:
+        with pytest.raises(L.LbmError) as ei:
+            lat.liquid_stats(0.1, rv, rl)          # not initialised
+        assert ei.value.status == L.LBM_ESTATE
+        lat.init_droplet(*w.droplet_centre(), w.R, w.W, rl, rv)
+        with pytest.raises(L.LbmError) as ei:
+            lat.liquid_stats(0.1, rl, rv)          # rho_l <= rho_v
+        assert ei.value.status == L.LBM_EINVAL
+        with pytest.raises(L.LbmError) as ei:
+            lat.liquid_stats(float("nan"), rv, rl)
+        assert ei.value.status == L.LBM_EINVAL
