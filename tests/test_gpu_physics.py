@@ -158,3 +158,56 @@ def test_surface_tension_and_its_tuning(L):
     assert r20 > 0.999 and r26 > 0.999
     assert abs(g0 - 0.01034) / 0.01034 < 0.10
     assert abs(g6 / g0 - 0.00395 / 0.01034) / (0.00395 / 0.01034) < 0.15
+
+
+def _sessile_angle(L, G_ads, n=128, nz=80, R=25.0, steps=8000):
+    """Static contact angle of a droplet resting on the wall z = 0 (piecewise EOS, D3Q27,
+    nu = 0.1): spherical-cap fit of the liquid area per plane (lbm_liquid_stats)."""
+    from paper_2306_16274_amd import impact
+    p = piecewise(L, (n, n, nz), Q=27)
+    p.G_ads = G_ads
+    p.rho_ref = 0.001
+    p.bc[2][0] = p.bc[2][1] = L.LBM_BC_WALL
+    with L.Lattice(p) as lat:
+        lat.init_droplet(n / 2, n / 2, 0.5 + 0.6 * R, R, 5.0, 1.0, 0.001)
+        v0 = lat.liquid_stats(0.5005, 0.001, 1.0)[2]
+        lat.step(steps)
+        counts, _, v1 = lat.liquid_stats(0.5005, 0.001, 1.0)
+    theta = impact.contact_angle_from_planes(counts)[0]
+    print(f"G_ads {G_ads}: theta {theta:.1f} deg, volume drift {v1 / v0 - 1:+.2e}")
+    return theta, v1 / v0 - 1
+
+
+def test_contact_angle_calibration(L):
+    """Sec. III E: the wetting force of Eq. (22) sets the contact angle monotonically in
+    G_ads. With psi at solid neighbours taken as psi of the fluid node, 90 degrees falls at
+    G_ads = 0.14 (not at 0 as the paper states: G_ads = 0 wets completely), the paper's 0.23
+    gives 129 degrees and about 157 degrees needs 0.28."""
+    th = {g: _sessile_angle(L, g) for g in (0.0, 0.14, 0.23, 0.28)}
+    assert th[0.0][0] < 30.0
+    assert abs(th[0.14][0] - 90.0) < 5.0
+    assert abs(th[0.23][0] - 129.0) < 6.0
+    assert 145.0 < th[0.28][0] < 165.0
+    assert th[0.0][0] < th[0.14][0] < th[0.23][0] < th[0.28][0]
+    assert all(abs(d) < 2e-3 for _, d in th.values())
+
+
+def test_impact_contact_time_on_superhydrophobic_wall(L):
+    """Sec. IV B reference case: R0 = 50 droplet at We = 10 on a wall of about 157 degrees,
+    nu_l = 0.0075 (nu_v = 0.05 through Eq. (24)), box 300 x 300 x 250, D3Q27 FP32 shifted.
+    The paper finds t_c / tau = 2.35 (universal scaling 2.2 +- 0.3); here 2.71. The liquid
+    volume stays within -1.5 % / +0.1 % (the paper: about +-1 %)."""
+    import math
+    from paper_2306_16274_amd import impact
+    gamma = 0.00963                     # Laplace law, D3Q27, kappa = 0, this EOS
+    U = math.sqrt(10.0 * gamma / 50.0)
+    case = impact.ImpactCase(U=U, G_ads=0.28)
+    out = impact.run_impact(case, 14000, every=50)
+    tau = impact.capillary_time(1.0, 50.0, gamma)
+    assert out["t_contact"] is not None and out["t_detach"] is not None
+    tc = (out["t_detach"] - out["t_contact"]) / tau
+    v = np.array(out["volume"]) / out["volume"][0]
+    print(f"t_c/tau {tc:.3f}, D_max/R0 {max(out['D_f']) / 50:.2f}, volume {v.min():.4f}..{v.max():.4f}")
+    assert 2.2 < tc < 3.0
+    assert 2.5 < max(out["D_f"]) / 50.0 < 3.5
+    assert v.min() > 0.985 and v.max() < 1.001
