@@ -479,7 +479,7 @@ static int default_fused_cfg(const lbm_ctx* c) {
         if (v >= 0 && v < kNumFusedCfgs && (!kFusedCfgs[v].fullx || c->p.nx == kFusedCfgs[v].tx))
             return v;
     }
-    return default_fused_cfg_index(c->p.nx, c->p.storage == LBM_FP64);
+    return default_fused_cfg_index(c->p.nx, c->p.storage == LBM_FP64, c->Q);
 }
 
 // Planes per z-chunk and tile order. Full-row tiles: 64-plane chunks (about one
@@ -487,9 +487,8 @@ static int default_fused_cfg(const lbm_ctx* c) {
 // chunks, XCD-contiguous tile ranges (neighbouring tiles then share an L2). Measured on
 // MI355X at 256^3 (D3Q19, FP32 and FP64).
 static void fused_chunking(const lbm_ctx* c, int& zc, int& remap) {
-    const bool fullx = kFusedCfgs[c->fused_cfg].fullx;
-    zc = fullx ? kFusedZcFullRow : kFusedZcTiled;
-    remap = fullx ? 0 : 1;
+    zc = default_fused_zc(kFusedCfgs[c->fused_cfg]);
+    remap = default_fused_remap(kFusedCfgs[c->fused_cfg]);
     if (const char* e = getenv("LBM_FUSED_ZC")) zc = std::max(1, atoi(e));      // tuning override
     if (const char* e = getenv("LBM_FUSED_REMAP")) remap = atoi(e) != 0;       // tuning override
     zc = std::min(zc, c->p.nz);
@@ -525,11 +524,40 @@ static void launch_fused_cfg(lbm_ctx* c, const void* fin, void* fout) {
     }
 }
 
+// Full-row tiles with the LDS prefetch (k_step_fused_pf): only for 4-byte storage and a
+// lattice whose tile buffers fit in LDS; other combinations never select it.
+template <int Q, typename T, int TX, int TY>
+static void launch_fused_pf(lbm_ctx* c, const void* fin, void* fout) {
+    if constexpr (sizeof(T) == 4 && fused_pf_lds_bytes(Q, TX, TY) <= kLdsBytesPerCU) {
+        const int nty = (c->p.ny + TY - 1) / TY;
+        int zc, remap;
+        fused_chunking(c, zc, remap);
+        const int nchunks = (c->p.nz + zc - 1) / zc;
+        const dim3 grid((unsigned)(nty * nchunks)), block(TX * TY);
+        switch (geom_of(c)) {
+        case GEOM_NONE:
+            hipLaunchKernelGGL((k_step_fused_pf<Q, T, GEOM_NONE, TX, TY>), grid, block, 0,
+                               c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), c->pf, zc, remap);
+            break;
+        case GEOM_WALLS:
+            hipLaunchKernelGGL((k_step_fused_pf<Q, T, GEOM_WALLS, TX, TY>), grid, block, 0,
+                               c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), c->pf, zc, remap);
+            break;
+        default:
+            hipLaunchKernelGGL((k_step_fused_pf<Q, T, GEOM_MASK, TX, TY>), grid, block, 0,
+                               c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), c->pf, zc, remap);
+        }
+    } else {
+        launch_fused_cfg<Q, T, TX, TY, true>(c, fin, fout);
+    }
+}
+
 template <int Q, typename T>
 static void launch_fused(lbm_ctx* c, const void* fin, void* fout) {
     switch (c->fused_cfg) {
     case 1: launch_fused_cfg<Q, T, 256, 2, true>(c, fin, fout); break;
     case 2: launch_fused_cfg<Q, T, 256, 4, true>(c, fin, fout); break;
+    case 3: launch_fused_pf<Q, T, 256, 4>(c, fin, fout); break;
     default: launch_fused_cfg<Q, T, 32, 8, false>(c, fin, fout); break;
     }
 }
