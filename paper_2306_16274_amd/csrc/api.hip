@@ -479,7 +479,7 @@ static int default_fused_cfg(const lbm_ctx* c) {
         if (v >= 0 && v < kNumFusedCfgs && (!kFusedCfgs[v].fullx || c->p.nx == kFusedCfgs[v].tx))
             return v;
     }
-    return default_fused_cfg_index(c->p.nx, c->p.storage == LBM_FP64, c->Q);
+    return default_fused_cfg_index(c->p.nx, (int)c->elem, c->Q);
 }
 
 // Planes per z-chunk and tile order. Full-row tiles: 64-plane chunks (about one
@@ -558,6 +558,7 @@ static void launch_fused(lbm_ctx* c, const void* fin, void* fout) {
     case 1: launch_fused_cfg<Q, T, 256, 2, true>(c, fin, fout); break;
     case 2: launch_fused_cfg<Q, T, 256, 4, true>(c, fin, fout); break;
     case 3: launch_fused_pf<Q, T, 256, 4>(c, fin, fout); break;
+    case 4: launch_fused_pf<Q, T, 256, 2>(c, fin, fout); break;
     default: launch_fused_cfg<Q, T, 32, 8, false>(c, fin, fout); break;
     }
 }

@@ -30,18 +30,16 @@
 
 namespace lbmk {
 
-// Launch configurations of k_step_fused: tile width and height, and whether the tile spans
-// the whole x row (then nx must equal tx). Defaults (from a sweep at 256^3 on MI355X):
-// full-row 256x4 tiles for 4-byte storage, 256x2 for FP64 (256x4 in FP64 needs more than 128
-// VGPRs and spills), 32x8 tiles for other widths. Full-row tiles march through 64-plane
+// Launch configurations of the fused step: tile width and height, whether the tile spans
+// the whole x row (then nx must equal tx), and pf: the next planes are prefetched into LDS
+// (k_step_fused_pf; 4-byte storage, and the populations of a tile plus its halo rows must fit
+// in LDS). 32x8 tiles serve widths other than 256. Full-row tiles march through 64-plane
 // z-chunks, in dispatch order without the prefetch and in XCD-contiguous order with it;
-// small tiles through 16-plane chunks in XCD-contiguous order. With the prefetch, 256x4 FP32
-// D3Q19 runs at 0.523 ms per 256^3 step against 0.536 ms for the plain tiles.
-// pf: full-row tiles whose next planes are prefetched into LDS (k_step_fused_pf; 4-byte
-// storage, and the lattice's populations of a tile plus its halo must fit in LDS).
+// small tiles through 16-plane chunks in XCD-contiguous order.
 struct FusedCfg { int tx, ty; bool fullx, pf; };
 constexpr FusedCfg kFusedCfgs[] = {{32, 8, false, false}, {256, 2, true, false},
-                                   {256, 4, true, false}, {256, 4, true, true}};
+                                   {256, 4, true, false}, {256, 4, true, true},
+                                   {256, 2, true, true}};
 constexpr int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
 constexpr int kFusedZcFullRow = 64, kFusedZcTiled = 16;
 
@@ -54,8 +52,18 @@ constexpr int kLdsBytesPerCU = 160 * 1024;
 constexpr int default_fused_zc(const FusedCfg& c) { return c.fullx ? kFusedZcFullRow : kFusedZcTiled; }
 constexpr int default_fused_remap(const FusedCfg& c) { return (!c.fullx || c.pf) ? 1 : 0; }
 
-constexpr int default_fused_cfg_index(int nx, bool fp64, int Q) {
-    return nx != 256 ? 0 : fp64 ? 1 : (fused_pf_lds_bytes(Q, 256, 4) <= kLdsBytesPerCU ? 3 : 2);
+// Default configuration for a 256-wide domain (measured at 256^3, ms per step):
+//   4-byte storage: prefetching 256x4 tiles where they fit in LDS (D3Q19: 0.506 vs 0.536
+//     plain), else prefetching 256x2 tiles (D3Q27: 0.800 vs 0.926 plain 256x2, 1.142 plain
+//     256x4, which spills);
+//   8-byte storage: plain 256x2 tiles (256x4 spills; D3Q27 2.52 vs 4.10);
+//   2-byte storage: plain 256x4 for D3Q19 (0.34 vs 0.38), plain 256x2 for D3Q27 (0.64 vs 0.92).
+constexpr int default_fused_cfg_index(int nx, int elem_bytes, int Q) {
+    return nx != 256 ? 0
+         : elem_bytes == 8 ? 1
+         : elem_bytes == 4 ? (fused_pf_lds_bytes(Q, 256, 4) <= kLdsBytesPerCU ? 3
+                              : fused_pf_lds_bytes(Q, 256, 2) <= kLdsBytesPerCU ? 4 : 1)
+         : (Q == 19 ? 2 : 1);
 }
 
 // Workgroup b -> tile index such that each XCD (b mod 8) gets a contiguous tile range.
@@ -274,18 +282,30 @@ __device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restr
 // Wait until every vector memory operation of this wavefront has completed (vmcnt(0); the
 // expcnt and lgkmcnt fields at their maxima, i.e. not waited for).
 __device__ __forceinline__ void wait_vector_memory() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// Workgroup barrier for LDS traffic only: every wavefront's LDS accesses complete, then
+// s_barrier. Unlike __syncthreads it does not wait for outstanding vector memory operations
+// (the asynchronous LDS loads in flight are read back only by the lanes that issued them,
+// after their own vmcnt wait). The memory clobber keeps the compiler from moving memory
+// accesses across it.
+__device__ __forceinline__ void barrier_lds() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+// Wait until every LDS access of this wavefront has completed (lgkmcnt(0); vmcnt and expcnt
+// at their maxima): LDS cells just read may then be overwritten by an asynchronous load.
+__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
 // One full-row tile of the fused step with the populations of the plane ahead streamed from
 // HBM straight into LDS (global_load_lds: no VGPRs held while in flight). With one
 // 1024-thread workgroup per CU the plain tile alternates a load phase and an arithmetic
-// phase; here the loads of plane z+2 are issued before the barrier and the collision of
-// plane z, and waited for only at the start of the next plane:
-//   wait for plane z+1 -> populations of z+1 from LDS into registers, psi(z+1) into the ring
-//   -> barrier -> read psi(z-1..z+1) of the own node's neighbourhood -> issue the loads of
-//   plane z+2 -> collide and store plane z.
+// phase; here the loads of plane z+2 are in flight while plane z is collided:
+//   wait for plane z+1 -> psi of the halo node from its LDS buffer -> refill that buffer
+//   with plane z+2 -> own populations of z+1 from LDS into registers, psi -> refill -> LDS
+//   barrier -> psi(z-1..z+1) of the neighbourhood from the ring -> collide and store z.
 // Each lane reads back only the LDS cells its own loads wrote, so the prefetch buffers need
-// no barrier; the ring slot written at plane z+1 was last read at plane z-1, one barrier
-// earlier. The arithmetic per node is the one of fused_tile (same functions, same order).
+// no barrier, and the barrier waits for LDS accesses only (a __syncthreads would also wait
+// for the loads in flight); the ring slot written at plane z+1 was last read at plane z-1,
+// one barrier earlier. The arithmetic per node is the one of fused_tile (same functions,
+// same order), so both give bitwise identical results.
 template <int Q, typename T, int GEOM, int TX, int TY>
 __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __restrict__ fout,
                                               const uint8_t* __restrict__ solid, const Grid& g,
@@ -365,8 +385,8 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
         }
         ring[slot][hy + 1][hx] = hv;
     };
-    // asynchronous pulls of plane zp into the LDS buffers
-    auto prefetch = [&](int zp) {
+    // asynchronous pulls of plane zp into the LDS buffers (own node, halo node)
+    auto prefetch_own = [&](int zp) {
         int zo[3];
         zoffs(zp, zo);
         const WallBits wb{wo.wx, wo.wy, zbits(zp)};
@@ -378,20 +398,38 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
                 reinterpret_cast<const char*>(fin) + ((unsigned)e * 4u + (unsigned)pop * pst),
                 LBM_LDS_PTR(&pf_own[i][wave * 64]), 4, 0, 0);
         }
-        if (has_halo) {
-            const WallBits hb{wh.wx, wh.wy, wb.wz};
+    };
+    auto prefetch_halo = [&](int zp) {
+        if (!has_halo) return;
+        int zo[3];
+        zoffs(zp, zo);
+        const WallBits hb{wh.wx, wh.wy, zbits(zp)};
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                int e, pop;
-                pull_source<Q, GEOM>(i, hxy, zo, solid, hb, e, pop);
-                __builtin_amdgcn_global_load_lds(
-                    reinterpret_cast<const char*>(fin) + ((unsigned)e * 4u + (unsigned)pop * pst),
-                    LBM_LDS_PTR(&pf_halo[i][wave * 64]), 4, 0, 0);
-            }
+        for (int i = 0; i < Q; ++i) {
+            int e, pop;
+            pull_source<Q, GEOM>(i, hxy, zo, solid, hb, e, pop);
+            __builtin_amdgcn_global_load_lds(
+                reinterpret_cast<const char*>(fin) + ((unsigned)e * 4u + (unsigned)pop * pst),
+                LBM_LDS_PTR(&pf_halo[i][wave * 64]), 4, 0, 0);
         }
     };
-    // plane zp from the LDS buffers: own populations into v, psi of own and halo node
-    auto take = [&](int zp, int slot, R* v) {
+    // plane zp from the LDS buffers: psi of the halo node; own populations into v and psi
+    auto take_halo = [&](int zp, int slot) {
+        if (!has_halo) return;
+        int zo[3];
+        zoffs(zp, zo);
+        const WallBits hb{wh.wx, wh.wy, zbits(zp)};
+        R hv;
+        if (node_solid<GEOM>(solid, hxy[4] + zo[1], hb)) hv = R(-1);
+        else {
+            R s = 0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) s += static_cast<R>(pf_halo[i][tid]);
+            hv = psi_of(s);
+        }
+        ring[slot][hy + 1][hx] = hv;
+    };
+    auto take_own = [&](int zp, int slot, R* v) {
         int zo[3];
         zoffs(zp, zo);
         const WallBits wb{wo.wx, wo.wy, zbits(zp)};
@@ -399,18 +437,6 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
         for (int i = 0; i < Q; ++i) v[i] = static_cast<R>(pf_own[i][tid]);
         ring[slot][ly + 1][lx] =
             node_solid<GEOM>(solid, oxy[4] + zo[1], wb) ? R(-1) : psi_of(sum_q<Q, R>(v));
-        if (has_halo) {
-            const WallBits hb{wh.wx, wh.wy, wb.wz};
-            R hv;
-            if (node_solid<GEOM>(solid, hxy[4] + zo[1], hb)) hv = R(-1);
-            else {
-                R s = 0;
-#pragma unroll
-                for (int i = 0; i < Q; ++i) s += static_cast<R>(pf_halo[i][tid]);
-                hv = psi_of(s);
-            }
-            ring[slot][hy + 1][hx] = hv;
-        }
     };
 
     R cur[Q], nxt[Q];
@@ -418,23 +444,30 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
     halo_psi(z0 - 1, 0);
     own_psi(z0, 1, cur);
     halo_psi(z0, 1);
-    prefetch(z0 + 1);
+    prefetch_halo(z0 + 1);
+    prefetch_own(z0 + 1);
     for (int z = z0; z < z1; ++z) {
         const int k = z - z0;
         const int s0 = k & 3, s1 = (k + 1) & 3, s2 = (k + 2) & 3;
+        const bool more = z + 1 < z1;
         wait_vector_memory();
-        take(z + 1, s2, nxt);
-        __syncthreads();
+        // each buffer is refilled with plane z+2 as soon as its plane z+1 has been read
+        take_halo(z + 1, s2);
+        wait_lds();
+        if (more) prefetch_halo(z + 2);
+        take_own(z + 1, s2, nxt);
+        wait_lds();
+        if (more) prefetch_own(z + 2);
+        barrier_lds();
         const R psi0 = ring[s1][ly + 1][lx];
-        R pn[Q];
-#pragma unroll
-        for (int j = 0; j < Q; ++j) {
-            const int ez = vel_z(j);
-            const int sl = ez < 0 ? s0 : (ez > 0 ? s2 : s1);
-            pn[j] = ring[sl][ly + 1 + vel_y(j)][col(vel_x(j))];
-        }
-        if (z + 1 < z1) prefetch(z + 2);
         if (active && !(psi0 < R(0))) {
+            R pn[Q];
+#pragma unroll
+            for (int j = 0; j < Q; ++j) {
+                const int ez = vel_z(j);
+                const int sl = ez < 0 ? s0 : (ez > 0 ? s2 : s1);
+                pn[j] = ring[sl][ly + 1 + vel_y(j)][col(vel_x(j))];
+            }
             const NodeForce<R> nf = node_force<Q, R>(psi0, pn, P);
             collide<Q, R>(cur, nf, P);
             const unsigned nb = (unsigned)(oxy[4] + z * nxy) * (unsigned)sizeof(T);

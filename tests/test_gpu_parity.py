@@ -260,12 +260,12 @@ def test_full_size_256_sampled_windows(L, storage):
 @pytest.mark.parametrize("geom", ["periodic", "walls", "cylinder"])
 @pytest.mark.parametrize("Q", [19, 27])
 def test_fused_prefetch_tiles_bitwise_equal_plain_tiles(L, monkeypatch, geom, Q):
-    """Full-row tiles with the LDS prefetch (launch configuration 3, the 256-wide FP32
-    default where the tile fits in LDS) against plain full-row tiles (configuration 2) and
-    against the 32x8 tiles (configuration 0): the per-node arithmetic is the same, so the
-    populations agree bit for bit. Ragged y extent (10 rows of 4-row tiles) and several
-    z-chunks (LBM_FUSED_ZC = 7 over nz = 20). D3Q27 does not fit the prefetch buffers and
-    falls back to plain tiles under configuration 3."""
+    """Full-row tiles with the LDS prefetch (launch configurations 3 = 256x4 and 4 = 256x2,
+    the 256-wide FP32 defaults) against plain full-row tiles (2 = 256x4, 1 = 256x2) and the
+    32x8 tiles (0): the per-node arithmetic is the same, so the populations agree bit for
+    bit. Ragged y extent (10 rows of 4-row tiles) and several z-chunks (LBM_FUSED_ZC = 7
+    over nz = 20). D3Q27 does not fit the 256x4 prefetch buffers and runs plain 256x4 tiles
+    under configuration 3."""
     walls = {"periodic": (), "walls": ("z_lo", "z_hi", "y_lo"), "cylinder": ("z_lo",)}[geom]
     cyl = (5.0, 9.0, 3.0) if geom == "cylinder" else None
     w = si.Workload("pf", Q, 256, 10, 20, T_over_Tc=0.7, walls=walls, cylinder=cyl, G_ads=0.05,
@@ -274,11 +274,11 @@ def test_fused_prefetch_tiles_bitwise_equal_plain_tiles(L, monkeypatch, geom, Q)
     rv, rl = maxwell(w)
     out = {}
     monkeypatch.setenv("LBM_FUSED_ZC", "7")
-    for cfg in ("3", "2", "0"):
+    for cfg in ("3", "4", "2", "1", "0"):
         monkeypatch.setenv("LBM_FUSED_CONFIG", cfg)
         with L.Lattice(gpu_params(w, "fp32", rho_ref=rv)) as lat:
             lat.init_droplet(*w.droplet_centre(), w.R, w.W, rl, rv, *w.U, w.noise, w.seed)
             lat.step(12)
             out[cfg] = lat.get_populations()
-    assert np.array_equal(out["3"], out["2"])
-    assert np.array_equal(out["3"], out["0"])
+    for cfg in ("4", "2", "1", "0"):
+        assert np.array_equal(out["3"], out[cfg]), cfg
