@@ -149,14 +149,16 @@ lbm_status lbm_moments(lbm_ctx* c, double* rho, double* u, double* p, double* to
    touches it) and the liquid volume (Sec. IV B). A fluid node is liquid when rho > threshold,
    with rho formed and compared in float64 exactly as lbm_moments returns it.
      count_z  NULL or nz int64: liquid nodes in each z plane (index k = plane z = k);
-     wetted   NULL or one int64: liquid nodes with at least one solid neighbour among the
-              lattice velocities;
+     wetted_z NULL or nz int64: liquid nodes of each z plane with a solid node at x + k e_i
+              for some lattice velocity e_i and 1 <= k <= reach (reach 1: a solid neighbour;
+              larger reach also counts liquid held off a hydrophobic wall by a thin vapour
+              layer);
      volume   NULL or one double: sum over fluid nodes of clamp((rho - rho_v)/(rho_l - rho_v),
               0, 1), a fixed-order float64 sum.
-   Errors: LBM_EINVAL unless rho_l > rho_v and all three are finite; LBM_ESTATE before
-   initialisation. Synchronous.                                                          */
+   Errors: LBM_EINVAL unless rho_l > rho_v, all three are finite and 1 <= reach <= 8;
+   LBM_ESTATE before initialisation. Synchronous.                                        */
 lbm_status lbm_liquid_stats(lbm_ctx* c, double threshold, double rho_v, double rho_l,
-                            int64_t* count_z, int64_t* wetted, double* volume);
+                            int32_t reach, int64_t* count_z, int64_t* wetted_z, double* volume);
 
 /* Measurement aid: run nsteps time steps (as lbm_step) with a HIP event pair around every
    kernel launch on the context stream, waiting after each step. avg_ms[k] receives the

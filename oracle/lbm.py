@@ -294,17 +294,20 @@ def totals(f, P, solid=None):
     return np.array([mass] + mom + [ek])
 
 
-def liquid_stats(f, P, threshold, rho_v, rho_l, solid=None):
+def liquid_stats(f, P, threshold, rho_v, rho_l, solid=None, reach=1):
     """Liquid-phase diagnostics at time t (Sec. IV A spreading film, Sec. IV B contact time
-    and liquid volume): liquid nodes (fluid, rho > threshold) per z plane, the liquid nodes
-    with a solid node at x + e_i for some lattice velocity e_i, and the liquid volume
-    sum over fluid nodes of clamp((rho - rho_v) / (rho_l - rho_v), 0, 1)."""
+    and liquid volume): liquid nodes (fluid, rho > threshold) per z plane, per z plane the
+    liquid nodes with a solid node at x + k e_i for some lattice velocity e_i and
+    1 <= k <= reach, and the liquid volume sum over fluid nodes of
+    clamp((rho - rho_v) / (rho_l - rho_v), 0, 1)."""
     if solid is None:
         solid = solid_mask(P)
     rho = f.sum(0)
     liquid = ~solid & (rho > threshold)
     touches = np.zeros(P.shape, dtype=bool)
-    for e in P.lat.e[1:]:
-        touches |= neighbour(solid, e)
+    for k in range(1, reach + 1):
+        for e in P.lat.e[1:]:
+            touches |= neighbour(solid, k * np.asarray(e))
     vol = np.clip((rho - rho_v) / (rho_l - rho_v), 0.0, 1.0)[~solid].sum()
-    return liquid.sum(axis=(1, 2)).astype(np.int64), int((liquid & touches).sum()), float(vol)
+    return (liquid.sum(axis=(1, 2)).astype(np.int64),
+            (liquid & touches).sum(axis=(1, 2)).astype(np.int64), float(vol))

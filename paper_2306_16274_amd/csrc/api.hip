@@ -817,22 +817,22 @@ extern "C" lbm_status lbm_moments(lbm_ctx* c, double* rho, double* u, double* p,
 
 template <int Q, typename T>
 struct LiquidFn {
-    static lbm_status run(lbm_ctx* c, double threshold, double rho_v, double rho_l,
-                          int64_t* count_z, int64_t* wetted, double* volume) {
+    static lbm_status run(lbm_ctx* c, double threshold, double rho_v, double rho_l, int reach,
+                          int64_t* count_z, int64_t* wetted_z, double* volume) {
         using R = typename Arith<T>::type;
         const Launch L = node_launch(c);
         const long long nb = nblocks(L), nz = c->p.nz;
         const long long per_plane = (long long)L.grid.x * L.grid.y;   // blocks of one z plane
         lbm_status st = ensure_partial(c, 3 * nb + 3 * nz + 3);
         if (st != LBM_OK) return st;
-        double* plane = c->partial + 3 * nb;       // nz rows: liquid, wetted, volume
+        double* plane = c->partial + 3 * nb;       // nz rows: liquid, in contact, volume
         double* tot = plane + 3 * nz;
         const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
                                                              ? (const void*)&c->pd : (const void*)&c->pf);
         launch_psi<Q, T>(c, c->f[c->cur]);
         hipLaunchKernelGGL((k_liquid_stats<Q, T>), L.grid, L.block, 0, c->stream,
                            (const T*)c->f[c->cur], (const R*)c->psi, c->partial, grid_of(c),
-                           P.rho_ref, threshold, rho_v, rho_l);
+                           P.rho_ref, threshold, rho_v, rho_l, reach);
         hipLaunchKernelGGL(k_sum_rows<3>, dim3((unsigned)nz), dim3(256), 0, c->stream,
                            c->partial, per_plane, plane);
         hipLaunchKernelGGL(k_sum_rows<3>, dim3(1), dim3(256), 0, c->stream, plane, nz, tot);
@@ -843,20 +843,24 @@ struct LiquidFn {
         HIPCHK(c, hipStreamSynchronize(c->stream));
         if (count_z)
             for (long long k = 0; k < nz; ++k) count_z[k] = (int64_t)h[(size_t)(3 * k)];
-        if (wetted) *wetted = (int64_t)h[(size_t)(3 * nz + 1)];
+        if (wetted_z)
+            for (long long k = 0; k < nz; ++k) wetted_z[k] = (int64_t)h[(size_t)(3 * k + 1)];
         if (volume) *volume = h[(size_t)(3 * nz + 2)];
         return LBM_OK;
     }
 };
 
 extern "C" lbm_status lbm_liquid_stats(lbm_ctx* c, double threshold, double rho_v, double rho_l,
-                                       int64_t* count_z, int64_t* wetted, double* volume) {
+                                       int32_t reach, int64_t* count_z, int64_t* wetted_z,
+                                       double* volume) {
     if (!c) return fail(nullptr, LBM_EINVAL, "null context");
     if (!c->initialised) return fail(c, LBM_ESTATE, "populations not initialised");
     if (!(rho_l > rho_v) || !std::isfinite(rho_l) || !std::isfinite(rho_v) || !std::isfinite(threshold))
         return fail(c, LBM_EINVAL, "need finite threshold and rho_l > rho_v");
+    if (reach < 1 || reach > 8) return fail(c, LBM_EINVAL, "reach must be in [1, 8]");
     HIPCHK(c, hipSetDevice(c->device));
-    lbm_status st = dispatch<LiquidFn>(c, threshold, rho_v, rho_l, count_z, wetted, volume);
+    lbm_status st = dispatch<LiquidFn>(c, threshold, rho_v, rho_l, (int)reach, count_z,
+                                       wetted_z, volume);
     if (st != LBM_OK) return st;
     return poll_health(c, true);
 }

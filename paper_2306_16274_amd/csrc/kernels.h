@@ -304,8 +304,9 @@ __global__ __launch_bounds__(256) void k_health_final(const double* __restrict__
 
 // Liquid diagnostics of the current state (Sec. IV A spreading diameter, Sec. IV B
 // contact time and liquid volume). Per block: the number of liquid fluid nodes
-// (rho > threshold), of those the ones with a solid neighbour (in contact with a wall or
-// the cylinder), and the liquid volume fraction sum clamp((rho - rho_v)/(rho_l - rho_v), 0, 1).
+// (rho > threshold), of those the ones with a solid node at x + k e_i for some lattice
+// velocity e_i and 1 <= k <= reach (in contact with a wall or the cylinder), and the liquid
+// volume fraction sum clamp((rho - rho_v)/(rho_l - rho_v), 0, 1).
 // rho is formed exactly as k_moments forms it (float64 sum of rho_ref and the zeroth
 // moment), so a threshold applied to the density field lbm_moments returns makes the same
 // decisions. Needs psi of the current state (solid marker) from k_density_psi.
@@ -314,7 +315,8 @@ __global__ __launch_bounds__(256) void k_liquid_stats(const T* __restrict__ fin,
                                                       const typename Arith<T>::type* __restrict__ psi,
                                                       double* __restrict__ partial, Grid g,
                                                       typename Arith<T>::type rho_ref,
-                                                      double threshold, double rho_v, double rho_l) {
+                                                      double threshold, double rho_v, double rho_l,
+                                                      int reach) {
     using R = typename Arith<T>::type;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -333,7 +335,19 @@ __global__ __launch_bounds__(256) void k_liquid_stats(const T* __restrict__ fin,
             R d[Q];
             gather<Q, T, R>(fin, g.stride, n, nb, snb, d);
             const double rho = (double)rho_ref + (double)forward<Q, R>(d).k000;
-            if (rho > threshold) { acc[0] = 1.0; acc[1] = touches ? 1.0 : 0.0; }
+            if (rho > threshold) {
+                for (int k = 2; k <= reach && !touches; ++k)
+#pragma unroll
+                    for (int j = 1; j < Q; ++j) {
+                        int c[3] = {x + k * vel_x(j), y + k * vel_y(j), z + k * vel_z(j)};
+                        const int n3[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) c[a] = ((c[a] % n3[a]) + n3[a]) % n3[a];
+                        touches |= psi[c[0] + g.nx * (c[1] + g.ny * c[2])] < R(0);
+                    }
+                acc[0] = 1.0;
+                acc[1] = touches ? 1.0 : 0.0;
+            }
             acc[2] = fmin(fmax((rho - rho_v) / (rho_l - rho_v), 0.0), 1.0);
         }
     }

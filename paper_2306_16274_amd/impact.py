@@ -146,24 +146,27 @@ def capillary_time(rho_l, R0, gamma):
     return math.sqrt(rho_l * R0 ** 3 / gamma)
 
 
-def run_impact(case, steps, every=50, stream=None, log=None, keep_going=False, contact_planes=2):
+def run_impact(case, steps, every=50, stream=None, log=None, keep_going=False, reach=2,
+               surface_top=None):
     """Run an impact case and sample the device diagnostics every `every` steps.
 
     Contact (Sec. IV B: from first touching the surface to bouncing off) is taken as liquid
-    present in the first `contact_planes` fluid layers above the wall (z = 1 .. contact_planes,
-    within that distance of the wall surface): on strongly hydrophobic walls the first layer
-    holds vapour even under a resting droplet, so liquid touching a solid node is not a
-    usable criterion there.
+    within `reach` lattice steps of a solid node (wall or cylinder) along a lattice
+    velocity, in the planes z < surface_top (default: the lower half of the box, so that a
+    rebounding droplet near the top wall does not count): on strongly hydrophobic walls the
+    first fluid layer holds vapour even under a resting droplet, so liquid next to a solid
+    node (reach 1) is not a usable criterion there.
 
-    Returns a dict with the series t, spreading diameter D_f (plane z = 1), liquid nodes
-    touching a solid, liquid volume, liquid nodes in the planes z = 1..8, the lowest liquid
-    plane and the liquid centroid height, plus t_contact (first sample in contact) and
-    t_detach (first later sample out of contact, None while still in contact).
-    keep_going: sample until `steps` even after the droplet has left the wall."""
+    Returns a dict with the series t, spreading diameter D_f (largest over the planes
+    z = 1 .. reach), liquid nodes in contact, liquid volume, liquid nodes in the planes
+    z = 1..8, the lowest liquid plane and the liquid centroid height, plus t_contact (first
+    sample in contact) and t_detach (first later sample out of contact, None while still in
+    contact). keep_going: sample until `steps` even after the droplet has left the solid."""
     p = case.params()
     if stream is not None:
         p.stream = stream
     thr = 0.5 * (case.rho_v + case.rho_l)
+    top = case.nz // 2 if surface_top is None else surface_top
     out = dict(t=[], D_f=[], wetted=[], volume=[], low=[], z_min=[], z_c=[],
                t_contact=None, t_detach=None)
     with L.Lattice(p, use_torch_stream=stream is None) as lat:
@@ -171,9 +174,10 @@ def run_impact(case, steps, every=50, stream=None, log=None, keep_going=False, c
         lat.init_droplet(cx, cy, cz, case.R0, case.W, case.rho_l, case.rho_v, 0.0, 0.0, -case.U)
         done = 0
         while True:
-            cz_, wet, vol = lat.liquid_stats(thr, case.rho_v, case.rho_l)
+            cz_, wz, vol = lat.liquid_stats(thr, case.rho_v, case.rho_l, reach)
+            wet = int(wz[:top].sum())
             out["t"].append(done)
-            out["D_f"].append(max(spreading_diameter(cz_, z) for z in range(1, contact_planes + 1)))
+            out["D_f"].append(max(spreading_diameter(cz_, z) for z in range(1, reach + 1)))
             out["wetted"].append(wet)
             out["volume"].append(vol)
             out["low"].append([int(v) for v in cz_[1:9]])
@@ -181,7 +185,7 @@ def run_impact(case, steps, every=50, stream=None, log=None, keep_going=False, c
             out["z_min"].append(int(nzl.min()) if nzl.size else -1)
             zz = np.arange(cz_.size)
             out["z_c"].append(float((zz * cz_).sum() / max(cz_.sum(), 1)))
-            touching = int(cz_[1:contact_planes + 1].sum()) > 0
+            touching = wet > 0
             if touching and out["t_contact"] is None:
                 out["t_contact"] = done
             if not touching and out["t_contact"] is not None and out["t_detach"] is None:

@@ -75,7 +75,7 @@ _SIGS = {
     "lbm_step": (ctypes.c_int, [_P, ctypes.c_int64]),
     "lbm_steps_done": (ctypes.c_int64, [_P]),
     "lbm_moments": (ctypes.c_int, [_P, _P, _P, _P, _P]),
-    "lbm_liquid_stats": (ctypes.c_int, [_P, _D, _D, _D, _P, _P, _P]),
+    "lbm_liquid_stats": (ctypes.c_int, [_P, _D, _D, _D, ctypes.c_int32, _P, _P, _P]),
     "lbm_synchronize": (ctypes.c_int, [_P]),
     "lbm_kernel_times": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, ctypes.c_int32, _P]),
     "lbm_coexistence": (ctypes.c_int, [ctypes.POINTER(lbm_params), ctypes.POINTER(_D),
@@ -184,14 +184,14 @@ def lbm_moments(ctx, shape, want=("rho", "u", "p", "totals")):
     return out
 
 
-def lbm_liquid_stats(ctx, nz, threshold, rho_v, rho_l):
-    """Returns (count_z int64 array of nz, wetted int, volume float)."""
+def lbm_liquid_stats(ctx, nz, threshold, rho_v, rho_l, reach=1):
+    """Returns (count_z, wetted_z: int64 arrays of nz, volume float)."""
     cz = np.empty(nz, dtype=np.int64)
-    wet = ctypes.c_int64(0)
+    wz = np.empty(nz, dtype=np.int64)
     vol = ctypes.c_double(0.0)
-    _check(library().lbm_liquid_stats(ctx, threshold, rho_v, rho_l, _ptr(cz),
-                                      ctypes.byref(wet), ctypes.byref(vol)), ctx)
-    return cz, int(wet.value), float(vol.value)
+    _check(library().lbm_liquid_stats(ctx, threshold, rho_v, rho_l, reach, _ptr(cz), _ptr(wz),
+                                      ctypes.byref(vol)), ctx)
+    return cz, wz, float(vol.value)
 
 
 def lbm_kernel_times(ctx, nsteps, cap=8):
@@ -292,8 +292,8 @@ class Lattice:
     def moments(self, want=("rho", "u", "p", "totals")):
         return lbm_moments(self.ctx, self.shape, want)
 
-    def liquid_stats(self, threshold, rho_v, rho_l):
-        return lbm_liquid_stats(self.ctx, self.shape[0], threshold, rho_v, rho_l)
+    def liquid_stats(self, threshold, rho_v, rho_l, reach=1):
+        return lbm_liquid_stats(self.ctx, self.shape[0], threshold, rho_v, rho_l, reach)
 
     def synchronize(self):
         lbm_synchronize(self.ctx)

@@ -27,8 +27,9 @@ def _sessile(Q):
                        noise=0.01, seed=5)
 
 
+@pytest.mark.parametrize("reach", [1, 2])
 @pytest.mark.parametrize("Q", [19, 27])
-def test_liquid_stats_fp64_matches_oracle(L, Q):
+def test_liquid_stats_fp64_matches_oracle(L, Q, reach):
     w = _sessile(Q)
     rv, rl = maxwell(w)
     thr = 0.5 * (rv + rl)
@@ -36,17 +37,17 @@ def test_liquid_stats_fp64_matches_oracle(L, Q):
     with L.Lattice(gpu_params(w, "fp64")) as lat:
         lat.init_droplet(cx, cy, cz, w.R, w.W, rl, rv, 0.0, 0.0, 0.0, w.noise, w.seed)
         lat.step(7)
-        counts, wet, vol = lat.liquid_stats(thr, rv, rl)
+        counts, wet, vol = lat.liquid_stats(thr, rv, rl, reach)
         f = lat.get_populations()
     P = oracle_params(w)
     solid = olbm.solid_mask(P)
-    oc, ow, ov = olbm.liquid_stats(f, P, thr, rv, rl, solid)
+    oc, ow, ov = olbm.liquid_stats(f, P, thr, rv, rl, solid, reach=reach)
     rho = f.sum(0)
     near = (np.abs(rho - thr) < 1e-12) & ~solid
-    print(f"Q{Q}: liquid {counts.sum()} wetted {wet} volume {vol:.6f}; near-threshold nodes {near.sum()}")
+    print(f"Q{Q}: liquid {counts.sum()} wetted {wet.sum()} volume {vol:.6f}; near-threshold nodes {near.sum()}")
     assert near.sum() == 0
     assert np.array_equal(counts, oc)
-    assert wet == ow and wet > 0
+    assert np.array_equal(wet, ow) and wet.sum() > 0
     assert abs(vol - ov) <= 1e-12 * ov
 
 
@@ -72,7 +73,7 @@ def test_liquid_stats_same_decisions_as_moments(L, storage, rho_ref):
             rho = lat.moments(want=("rho",))["rho"]
             liquid = ~solid & (rho > thr)
             assert np.array_equal(counts, liquid.sum(axis=(1, 2)))
-            assert wet == int((liquid & touches).sum())
+            assert np.array_equal(wet, (liquid & touches).sum(axis=(1, 2)))
             v = np.clip((rho - rv) / (rl - rv), 0.0, 1.0)[~solid].sum()
             assert abs(vol - v) <= 1e-12 * v
 
@@ -91,3 +92,7 @@ def test_liquid_stats_rejects_bad_arguments(L):
         with pytest.raises(L.LbmError) as ei:
             lat.liquid_stats(float("nan"), rv, rl)
         assert ei.value.status == L.LBM_EINVAL
+        for reach in (0, 9):
+            with pytest.raises(L.LbmError) as ei:
+                lat.liquid_stats(0.1, rv, rl, reach)
+            assert ei.value.status == L.LBM_EINVAL
