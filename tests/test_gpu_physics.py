@@ -130,7 +130,7 @@ def test_single_relaxation_time_diverges_where_mrt_does_not(L):
     assert np.isfinite(tot).all()
 
 
-def surface_tension(L, kappa, radii=(20, 26, 32, 38), n=128, steps=6000):
+def surface_tension(L, kappa, radii=(28, 33, 38, 43, 48), n=180, steps=8000):
     """Laplace law dp = 2 gamma / R (Sec. III C): slope of p_in - p_out (bulk pressure of
     Eq. (17)) against 2 / R_eff, R_eff from the liquid volume."""
     c = n / 2
@@ -153,15 +153,16 @@ def surface_tension(L, kappa, radii=(20, 26, 32, 38), n=128, steps=6000):
 
 
 def test_surface_tension_and_its_tuning(L):
-    """Sec. III E prints 0.00395 <= gamma <= 0.01034 for 0 <= kappa <= 0.6 with this EOS:
-    gamma(0) within 10 % of 0.01034 and gamma(0.6)/gamma(0) within 15 % of the printed
-    ratio 0.382 (Eq. (B6) predicts 1 - kappa = 0.4). Laplace's law is linear (R^2 > 0.999)."""
+    """Sec. III C/E: droplets R0 = 28..48 in a 180^3 box; the paper prints
+    0.00395 <= gamma <= 0.01034 for 0 <= kappa <= 0.6 with this EOS: gamma(0) within 5 % of
+    0.01034 (here 0.0101) and gamma(0.6)/gamma(0) within 8 % of the printed ratio 0.382
+    (here 0.363; Eq. (B6) predicts 1 - kappa = 0.4). Laplace's law is linear (R^2 > 0.995)."""
     g0, r20 = surface_tension(L, 0.0)
     g6, r26 = surface_tension(L, 0.6)
     print(f"gamma(0) {g0:.5f} gamma(0.6) {g6:.5f} ratio {g6 / g0:.3f}")
-    assert r20 > 0.999 and r26 > 0.999
-    assert abs(g0 - 0.01034) / 0.01034 < 0.10
-    assert abs(g6 / g0 - 0.00395 / 0.01034) / (0.00395 / 0.01034) < 0.15
+    assert r20 > 0.995 and r26 > 0.995
+    assert abs(g0 - 0.01034) / 0.01034 < 0.05
+    assert abs(g6 / g0 - 0.00395 / 0.01034) / (0.00395 / 0.01034) < 0.08
 
 
 def _sessile_angle(L, G_ads, n=128, nz=80, R=25.0, steps=8000):
@@ -199,11 +200,11 @@ def test_contact_angle_calibration(L):
 def test_impact_contact_time_on_superhydrophobic_wall(L):
     """Sec. IV B reference case: R0 = 50 droplet at We = 10 on a wall of about 157 degrees,
     nu_l = 0.0075 (nu_v = 0.05 through Eq. (24)), box 300 x 300 x 250, D3Q27 FP32 shifted.
-    The paper finds t_c / tau = 2.35 (universal scaling 2.2 +- 0.3); here 2.71. The liquid
+    The paper finds t_c / tau = 2.35 (universal scaling 2.2 +- 0.3); here 2.78. The liquid
     volume stays within -1.5 % / +0.1 % (the paper: about +-1 %)."""
     import math
     from paper_2306_16274_amd import impact
-    gamma = 0.00963                     # Laplace law, D3Q27, kappa = 0, this EOS
+    gamma = 0.01007                     # Laplace law, D3Q27, kappa = 0, this EOS (180^3)
     U = math.sqrt(10.0 * gamma / 50.0)
     case = impact.ImpactCase(U=U, G_ads=0.28)
     out = impact.run_impact(case, 14000, every=50)
@@ -220,10 +221,10 @@ def test_impact_contact_time_on_superhydrophobic_wall(L):
 def test_impact_on_cylinder_shortens_contact(L):
     """Sec. IV B, Fig. 9: a cylinder of radius 0.4 R0 lying on the super-hydrophobic wall
     shortens the contact of the We = 10 droplet (the paper: t_c/tau 2.35 -> 1.79, -24 %; here
-    2.71 -> 2.11, -22 %). The liquid volume stays within -1.5 % / +0.1 %."""
+    2.78 -> 2.14, -23 %). The liquid volume stays within -1.5 % / +0.1 %."""
     import math
     from paper_2306_16274_amd import impact
-    gamma = 0.00963
+    gamma = 0.01007
     U = math.sqrt(10.0 * gamma / 50.0)
     tau = impact.capillary_time(1.0, 50.0, gamma)
     out = impact.run_impact(impact.ImpactCase(U=U, G_ads=0.28, r_cyl=20.0), 14000, every=50)
@@ -232,7 +233,7 @@ def test_impact_on_cylinder_shortens_contact(L):
     v = np.array(out["volume"]) / out["volume"][0]
     print(f"cylinder R/R0 = 0.4: t_c/tau {tc:.3f}, volume {v.min():.4f}..{v.max():.4f}")
     assert 1.6 < tc < 2.4
-    assert tc < 0.85 * 2.71
+    assert tc < 0.85 * 2.78
     assert v.min() > 0.985 and v.max() < 1.001
 
 
