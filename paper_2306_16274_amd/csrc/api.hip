@@ -486,9 +486,11 @@ static int default_fused_cfg(const lbm_ctx* c) {
 // workgroup per CU slot at 256^3), dispatch order left as is. Small tiles: 16-plane
 // chunks, XCD-contiguous tile ranges (neighbouring tiles then share an L2). Measured on
 // MI355X at 256^3 (D3Q19, FP32 and FP64).
-static void fused_chunking(const lbm_ctx* c, int& zc, int& remap) {
+static void fused_chunking(const lbm_ctx* c, int& zc, int& remap, int& hints) {
     zc = default_fused_zc(kFusedCfgs[c->fused_cfg]);
     remap = default_fused_remap(kFusedCfgs[c->fused_cfg]);
+    hints = default_fused_hints(kFusedCfgs[c->fused_cfg], (int)c->elem);
+    if (const char* e = getenv("LBM_FUSED_HINTS")) hints = atoi(e);            // tuning override
     if (const char* e = getenv("LBM_FUSED_ZC")) zc = std::max(1, atoi(e));      // tuning override
     if (const char* e = getenv("LBM_FUSED_REMAP")) remap = atoi(e) != 0;       // tuning override
     zc = std::min(zc, c->p.nz);
@@ -501,8 +503,8 @@ static void launch_fused_cfg(lbm_ctx* c, const void* fin, void* fout) {
                                                          ? (const void*)&c->pd : (const void*)&c->pf);
     const int ntx = (c->p.nx + TX - 1) / TX, nty = (c->p.ny + TY - 1) / TY;
     const long long tiles = (long long)ntx * nty;
-    int zc, remap;
-    fused_chunking(c, zc, remap);
+    int zc, remap, hints;
+    fused_chunking(c, zc, remap, hints);
     const int nchunks = (c->p.nz + zc - 1) / zc;
     const dim3 grid((unsigned)(tiles * nchunks)), block(TX * TY);
     // the kernel addresses populations with 32-bit byte offsets (checked at create)
@@ -510,17 +512,17 @@ static void launch_fused_cfg(lbm_ctx* c, const void* fin, void* fout) {
     case GEOM_NONE:
         hipLaunchKernelGGL((k_step_fused<Q, T, GEOM_NONE, TX, TY, FULLX>), grid, block, 0,
                            c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), P, ntx, nty,
-                           zc, remap);
+                           zc, remap, hints);
         break;
     case GEOM_WALLS:
         hipLaunchKernelGGL((k_step_fused<Q, T, GEOM_WALLS, TX, TY, FULLX>), grid, block, 0,
                            c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), P, ntx, nty,
-                           zc, remap);
+                           zc, remap, hints);
         break;
     default:
         hipLaunchKernelGGL((k_step_fused<Q, T, GEOM_MASK, TX, TY, FULLX>), grid, block, 0,
                            c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), P, ntx, nty,
-                           zc, remap);
+                           zc, remap, hints);
     }
 }
 
@@ -530,22 +532,25 @@ template <int Q, typename T, int TX, int TY>
 static void launch_fused_pf(lbm_ctx* c, const void* fin, void* fout) {
     if constexpr (sizeof(T) == 4 && fused_pf_lds_bytes(Q, TX, TY) <= kLdsBytesPerCU) {
         const int nty = (c->p.ny + TY - 1) / TY;
-        int zc, remap;
-        fused_chunking(c, zc, remap);
+        int zc, remap, hints;
+        fused_chunking(c, zc, remap, hints);
         const int nchunks = (c->p.nz + zc - 1) / zc;
         const dim3 grid((unsigned)(nty * nchunks)), block(TX * TY);
         switch (geom_of(c)) {
         case GEOM_NONE:
             hipLaunchKernelGGL((k_step_fused_pf<Q, T, GEOM_NONE, TX, TY>), grid, block, 0,
-                               c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), c->pf, zc, remap);
+                               c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), c->pf, zc, remap,
+                               hints);
             break;
         case GEOM_WALLS:
             hipLaunchKernelGGL((k_step_fused_pf<Q, T, GEOM_WALLS, TX, TY>), grid, block, 0,
-                               c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), c->pf, zc, remap);
+                               c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), c->pf, zc, remap,
+                               hints);
             break;
         default:
             hipLaunchKernelGGL((k_step_fused_pf<Q, T, GEOM_MASK, TX, TY>), grid, block, 0,
-                               c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), c->pf, zc, remap);
+                               c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), c->pf, zc, remap,
+                               hints);
         }
     } else {
         launch_fused_cfg<Q, T, TX, TY, true>(c, fin, fout);

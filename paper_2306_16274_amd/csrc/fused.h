@@ -30,6 +30,14 @@
 
 namespace lbmk {
 
+// Cache hints of the fused step (bit flags, uniform per launch):
+//   kHintNtStore      populations written by a step are stored with the nontemporal hint
+//                     (not read again within the step, so they need not displace the halo
+//                     rows other tiles are about to pull);
+//   kHintNtInterior   prefetching tiles load the own pulls of their interior rows (read by
+//                     no other tile) with the nontemporal hint.
+constexpr int kHintNtStore = 1, kHintNtInterior = 2;
+
 // Launch configurations of the fused step: tile width and height, whether the tile spans
 // the whole x row (then nx must equal tx), and pf: the next planes are prefetched into LDS
 // (k_step_fused_pf; 4-byte storage, and the populations of a tile plus its halo rows must fit
@@ -51,6 +59,9 @@ constexpr int kLdsBytesPerCU = 160 * 1024;
 
 constexpr int default_fused_zc(const FusedCfg& c) { return c.fullx ? kFusedZcFullRow : kFusedZcTiled; }
 constexpr int default_fused_remap(const FusedCfg& c) { return (!c.fullx || c.pf) ? 1 : 0; }
+constexpr int default_fused_hints(const FusedCfg& c, int elem_bytes) {
+    return (c.pf || elem_bytes != 8) ? kHintNtStore : 0;
+}
 
 // Default configuration for a 256-wide domain (measured at 256^3, ms per step):
 //   4-byte storage: prefetching 256x4 tiles where they fit in LDS (D3Q19: 0.506 vs 0.536
@@ -80,6 +91,11 @@ __device__ __forceinline__ T ld_off(const T* __restrict__ base, unsigned byte_of
 template <typename T>
 __device__ __forceinline__ void st_off(T* __restrict__ base, unsigned byte_off, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+// Streaming store (nontemporal hint).
+template <typename T>
+__device__ __forceinline__ void st_off_nt(T* __restrict__ base, unsigned byte_off, T v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off));
 }
 
 // How a kernel learns which nodes are solid: none (fully periodic), wall layers only
@@ -155,7 +171,7 @@ template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX>
 __device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restrict__ fout,
                                            const uint8_t* __restrict__ solid, const Grid& g,
                                            const Phys<typename Arith<T>::type>& P,
-                                           int t, int ntx, int nty, int zc) {
+                                           int t, int ntx, int nty, int zc, int hints) {
     using R = typename Arith<T>::type;
     constexpr int LX = FULLX ? TX : TX + 2, LY = TY + 2;
     constexpr int OX = FULLX ? 0 : 1;                 // LDS column of tile column 0
@@ -256,8 +272,13 @@ __device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restr
             const NodeForce<R> nf = node_force<Q, R>(psi0, pn, P);
             collide<Q, R>(c, nf, P);
             const unsigned nb = (unsigned)(oxy[4] + z * nxy) * (unsigned)sizeof(T);
+            if (hints & kHintNtStore) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) st_off(fout, nb + (unsigned)i * pst, static_cast<T>(c[i]));
+                for (int i = 0; i < Q; ++i) st_off_nt(fout, nb + (unsigned)i * pst, static_cast<T>(c[i]));
+            } else {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) st_off(fout, nb + (unsigned)i * pst, static_cast<T>(c[i]));
+            }
         }
     };
 
@@ -309,11 +330,11 @@ __device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F);
 template <int Q, typename T, int GEOM, int TX, int TY>
 __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __restrict__ fout,
                                               const uint8_t* __restrict__ solid, const Grid& g,
-                                              const Phys<float>& P, int t, int zc) {
+                                              const Phys<float>& P, int t, int zc, int hints) {
     static_assert(sizeof(T) == 4, "the LDS prefetch moves 4-byte elements");
     using R = float;
     constexpr int NT = TX * TY, H = 2 * TX;
-    static_assert(H % 64 == 0 && H <= NT, "halo rows must be whole wavefronts");
+    static_assert(H % 64 == 0 && H <= NT && TX % 64 == 0, "rows must be whole wavefronts");
     static_assert(fused_pf_lds_bytes(Q, TX, TY) <= kLdsBytesPerCU, "tile does not fit in LDS");
     __shared__ R ring[4][TY + 2][TX];
     __shared__ T pf_own[Q][NT];
@@ -386,17 +407,31 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
         ring[slot][hy + 1][hx] = hv;
     };
     // asynchronous pulls of plane zp into the LDS buffers (own node, halo node)
+    // Own pulls of the interior rows are read by no other tile (kHintNtInterior). A
+    // wavefront covers part of one row (TX is a multiple of 64), so the choice is uniform.
+    const bool interior_row = (hints & kHintNtInterior) && ly != 0 && ly != TY - 1;
     auto prefetch_own = [&](int zp) {
         int zo[3];
         zoffs(zp, zo);
         const WallBits wb{wo.wx, wo.wy, zbits(zp)};
+        if (interior_row) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            int e, pop;
-            pull_source<Q, GEOM>(i, oxy, zo, solid, wb, e, pop);
-            __builtin_amdgcn_global_load_lds(
-                reinterpret_cast<const char*>(fin) + ((unsigned)e * 4u + (unsigned)pop * pst),
-                LBM_LDS_PTR(&pf_own[i][wave * 64]), 4, 0, 0);
+            for (int i = 0; i < Q; ++i) {
+                int e, pop;
+                pull_source<Q, GEOM>(i, oxy, zo, solid, wb, e, pop);
+                __builtin_amdgcn_global_load_lds(
+                    reinterpret_cast<const char*>(fin) + ((unsigned)e * 4u + (unsigned)pop * pst),
+                    LBM_LDS_PTR(&pf_own[i][wave * 64]), 4, 0, 2);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                int e, pop;
+                pull_source<Q, GEOM>(i, oxy, zo, solid, wb, e, pop);
+                __builtin_amdgcn_global_load_lds(
+                    reinterpret_cast<const char*>(fin) + ((unsigned)e * 4u + (unsigned)pop * pst),
+                    LBM_LDS_PTR(&pf_own[i][wave * 64]), 4, 0, 0);
+            }
         }
     };
     auto prefetch_halo = [&](int zp) {
@@ -471,8 +506,14 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
             const NodeForce<R> nf = node_force<Q, R>(psi0, pn, P);
             collide<Q, R>(cur, nf, P);
             const unsigned nb = (unsigned)(oxy[4] + z * nxy) * (unsigned)sizeof(T);
+            if (hints & kHintNtStore) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) st_off(fout, nb + (unsigned)i * pst, static_cast<T>(cur[i]));
+                for (int i = 0; i < Q; ++i)
+                    st_off_nt(fout, nb + (unsigned)i * pst, static_cast<T>(cur[i]));
+            } else {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) st_off(fout, nb + (unsigned)i * pst, static_cast<T>(cur[i]));
+            }
         }
 #pragma unroll
         for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
@@ -484,9 +525,9 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_pf(const T* __restrict__
                                                           T* __restrict__ fout,
                                                           const uint8_t* __restrict__ solid,
                                                           Grid g, Phys<float> P, int zc,
-                                                          int remap) {
+                                                          int remap, int hints) {
     const int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    fused_tile_pf<Q, T, GEOM, TX, TY>(fin, fout, solid, g, P, t, zc);
+    fused_tile_pf<Q, T, GEOM, TX, TY>(fin, fout, solid, g, P, t, zc, hints);
 }
 
 // Single domain. remap != 0: map workgroups to tiles so that each XCD gets a contiguous
@@ -496,9 +537,10 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(const T* __restrict__ fi
                                                        T* __restrict__ fout,
                                                        const uint8_t* __restrict__ solid,
                                                        Grid g, Phys<typename Arith<T>::type> P,
-                                                       int ntx, int nty, int zc, int remap) {
+                                                       int ntx, int nty, int zc, int remap,
+                                                       int hints) {
     const int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    fused_tile<Q, T, GEOM, TX, TY, FULLX>(fin, fout, solid, g, P, t, ntx, nty, zc);
+    fused_tile<Q, T, GEOM, TX, TY, FULLX>(fin, fout, solid, g, P, t, ntx, nty, zc, hints);
 }
 
 // One domain of a batched step: its buffers, geometry, physics and the first workgroup
@@ -526,7 +568,7 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_batch(const DomainDesc<T
     }
     const DomainDesc<T>& D = d[lo];
     fused_tile<Q, T, GEOM, TX, TY, false>(D.fin, D.fout, D.solid, D.g, D.P, b - D.block0,
-                                                D.ntx, D.nty, D.zc);
+                                                D.ntx, D.nty, D.zc, kHintNtStore);
 }
 
 }  // namespace lbmk
