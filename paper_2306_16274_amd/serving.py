@@ -100,17 +100,16 @@ def start_job(req, storage, stream, t_now):
 
 
 def finish_job(job):
-    """Read the result of a finished request: total mass drift and the spreading diameter
-    (diameter of the equal-area disc of liquid nodes in the first fluid layer, z = 1)."""
-    m = job.lat.moments(want=("rho", "totals"))
-    rho = m["rho"]
+    """Read the result of a finished request, reduced on the device: the spreading diameter
+    (diameter of the equal-area disc of the liquid nodes in the first fluid layer, z = 1,
+    Sec. IV A), the liquid volume and the total mass."""
     thr = 0.5 * (job.rho_l + job.rho_v)
-    area = float(np.count_nonzero(rho[1] > thr))
-    d_f = 2.0 * math.sqrt(area / math.pi)
-    mass = float(m["totals"][0])
+    counts, _, volume = job.lat.liquid_stats(thr, job.rho_v, job.rho_l)
+    d_f = 2.0 * math.sqrt(float(counts[1]) / math.pi)
+    mass = float(job.lat.moments(want=("totals",))["totals"][0])
     job.lat.close()
     return dict(spread_diameter=d_f, spread_ratio=d_f / float(job.req["R"]), mass=mass,
-                finite=bool(np.isfinite(mass)))
+                liquid_volume=volume, finite=bool(np.isfinite(mass)))
 
 
 def serve(trace, mode="batched", storage="fp32", budget_bytes=64 << 30, max_slots=64,

@@ -282,3 +282,81 @@ def test_fused_prefetch_tiles_bitwise_equal_plain_tiles(L, monkeypatch, geom, Q)
             out[cfg] = lat.get_populations()
     for cfg in ("4", "2", "1", "0"):
         assert np.array_equal(out["3"], out[cfg]), cfg
+
+
+def _sampled_window_errors(w, f3, f4, centres, solid=None, h=6):
+    """Advance 13^3 windows of the read-back state f3 one step with the oracle (the solid
+    mask, if any, cut from the full domain) and return the worst pointwise relative rho
+    error and population error of the GPU's next state f4 on their inner 9^3."""
+    inner = slice(2, -2)
+    Pw = oracle_params(w.with_(nx=2 * h + 1, ny=2 * h + 1, nz=2 * h + 1, walls=(), cylinder=None))
+    worst_rho, worst_f = 0.0, 0.0
+    for (z, y, x) in centres:
+        z, y, x = int(z), int(y), int(x)
+        sw = None if solid is None else _window(solid[None], z, y, x, h)[0]
+        fo = olbm.step(_window(f3, z, y, x, h), Pw, solid=sw)[:, inner, inner, inner]
+        fg = _window(f4, z, y, x, h)[:, inner, inner, inner]
+        fl = np.ones(fo.shape[1:], bool) if sw is None else ~sw[inner, inner, inner]
+        if not fl.any():
+            continue
+        rho_o, rho_g = fo.sum(0)[fl], fg.sum(0)[fl]
+        worst_rho = max(worst_rho, float(np.max(np.abs(rho_g - rho_o) / rho_o)))
+        worst_f = max(worst_f, float(np.max(np.abs(fg[:, fl] - fo[:, fl]))))
+    return worst_rho, worst_f
+
+
+def test_full_size_impact_384x384x192_sampled_windows(L):
+    """The droplet-impact workload at full size (384 x 384 x 192 D3Q19, walls z = 0 and
+    z = 191, CS at 0.55 T_c, R = 40 at z = 50 falling at 0.05, nu = 0.001, FP32 shifted
+    storage) in its default launch configuration (32x8 tiles): one GPU step from a
+    read-back state against the oracle on windows at both walls, the droplet's foot,
+    interface and interior, the vapour and random places. G_ads = 0 (the config's 90 degree
+    wall is nominal: the wetting force enters through the same code path at any value)."""
+    w = si.IMPACT_384
+    rv, rl = maxwell(w)
+    cx, cy, cz = w.droplet_centre()
+    with L.Lattice(gpu_params(w, "fp32", rho_ref=rv)) as lat:
+        lat.init_droplet(cx, cy, cz, w.R, w.W, rl, rv, *w.U, w.noise, w.seed)
+        lat.step(3)
+        f3 = lat.get_populations()
+        lat.step(1)
+        f4 = lat.get_populations()
+    solid = olbm.solid_mask(oracle_params(w))
+    rng = np.random.default_rng(384)
+    centres = [(1, cy, cx), (5, cy, cx), (cz - w.R, cy, cx), (cz, cy, cx + w.R), (cz, cy, cx),
+               (190, 10, 370), (96, 0, 0), (cz, cy - w.R, cx)]
+    centres += [(int(rng.integers(0, 192)), int(rng.integers(0, 384)), int(rng.integers(0, 384)))
+                for _ in range(6)]
+    er, ef = _sampled_window_errors(w, f3, f4, centres, solid)
+    print(f"384x384x192 fp32: worst relative rho {er:.2e}, worst |df| {ef:.2e}")
+    assert er < 1e-6
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp64", "fp16"])
+def test_full_size_cylinder_d3q27_sampled_windows(L, storage):
+    """The D3Q27 cylinder-impact workload at full size (320 x 256 x 192, walls z = 0 and
+    z = 191, cylinder of radius 20 along x resting on the wall, CS at 0.6 T_c, R = 30
+    falling at 0.04, wetting G_ads = 0.2): one GPU step against the oracle on windows on the
+    cylinder surface, the wall, the droplet and random places. FP64 to 1e-12 relative in
+    rho; FP32 shifted storage to 1e-6; FP16 shifted storage reported (bound 5e-3)."""
+    w = si.CYLINDER_D3Q27
+    rv, rl = maxwell(w)
+    ref = 0.0 if storage == "fp64" else rv
+    cx, cy, cz = w.droplet_centre()
+    with L.Lattice(gpu_params(w, storage, rho_ref=ref)) as lat:
+        lat.init_droplet(cx, cy, cz, w.R, w.W, rl, rv, *w.U, w.noise, w.seed)
+        lat.step(3)
+        f3 = lat.get_populations()
+        lat.step(1)
+        f4 = lat.get_populations()
+    solid = olbm.solid_mask(oracle_params(w))
+    yc, zc, r = w.cylinder
+    rng = np.random.default_rng(320)
+    centres = [(int(zc + r + 1), int(yc), 100), (int(zc), int(yc + r + 1), 7), (1, 30, 300),
+               (int(zc + r * 0.7 + 1), int(yc + r * 0.7 + 1), 319), (cz, cy, cx), (cz - w.R, cy, cx),
+               (cz, cy + w.R, cx), (190, 255, 0)]
+    centres += [(int(rng.integers(0, 192)), int(rng.integers(0, 256)), int(rng.integers(0, 320)))
+                for _ in range(6)]
+    er, ef = _sampled_window_errors(w, f3, f4, centres, solid)
+    print(f"320x256x192 D3Q27 {storage}: worst relative rho {er:.2e}, worst |df| {ef:.2e}")
+    assert er < {"fp64": 1e-12, "fp32": 1e-6, "fp16": 5e-3}[storage]

@@ -96,4 +96,5 @@ def test_serving_results_same_alone_and_in_the_mix(L):
     for r in rb["records"]:
         s = by_id[r["id"]]
         assert r["mass"] == s["mass"] and r["spread_diameter"] == s["spread_diameter"], r["id"]
+        assert r["liquid_volume"] == s["liquid_volume"], r["id"]
         assert r["finite"]

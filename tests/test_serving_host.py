@@ -1,0 +1,139 @@
+"""Host logic of the continuous-batching loop, on the CPU: the lattice and batch entry
+points are replaced by stand-ins that count steps and memory, while request parameters,
+coexistence densities and footprints come from the library's host-only entry points."""
+import threading
+
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from paper_2306_16274_amd import lbm as L
+from paper_2306_16274_amd import serving
+
+
+class Recorder:
+    def __init__(self):
+        self.lock = threading.Lock()
+        self.alive = {}            # ctx -> device footprint in bytes
+        self.steps = {}            # ctx -> steps taken
+        self.closed = {}           # ctx -> steps at close
+        self.peak_bytes = 0
+        self.peak_alive = 0
+        self.log = []              # ctx of every step call, in order
+
+
+def install_fakes(monkeypatch, rec):
+    class FakeLattice:
+        _next = [1]
+
+        def __init__(self, params, use_torch_stream=True):
+            with rec.lock:
+                self.ctx = FakeLattice._next[0]
+                FakeLattice._next[0] += 1
+                self.nz = params.nz
+                rec.alive[self.ctx] = L.lbm_footprint_bytes(params)
+                rec.steps[self.ctx] = 0
+                rec.peak_bytes = max(rec.peak_bytes, sum(rec.alive.values()))
+                rec.peak_alive = max(rec.peak_alive, len(rec.alive))
+
+        def init_droplet(self, *a, **k):
+            pass
+
+        def step(self, n=1):
+            with rec.lock:
+                rec.steps[self.ctx] += n
+                rec.log.append(self.ctx)
+
+        def synchronize(self):
+            pass
+
+        def liquid_stats(self, thr, rv, rl, reach=1):
+            c = np.zeros(self.nz, dtype=np.int64)
+            c[1] = 100
+            return c, np.zeros(self.nz, dtype=np.int64), 1.0
+
+        def moments(self, want=()):
+            return {"totals": np.array([1.0, 0, 0, 0, 0])}
+
+        def close(self):
+            with rec.lock:
+                rec.closed[self.ctx] = rec.steps[self.ctx]
+                rec.alive.pop(self.ctx, None)
+
+    class FakeBatch:
+        def __init__(self, ctxs, spl):
+            self.ctxs, self.spl = list(ctxs), spl
+
+    def batch_create(ctxs, spl, stream=None):
+        return FakeBatch(ctxs, spl)
+
+    def batch_run(b, n):
+        with rec.lock:
+            for c in b.ctxs:
+                assert c in rec.alive, "batched a lattice that was already freed"
+                rec.steps[c] += n * b.spl
+
+    monkeypatch.setattr(serving.L, "Lattice", FakeLattice)
+    monkeypatch.setattr(serving.L, "lbm_batch_create", batch_create)
+    monkeypatch.setattr(serving.L, "lbm_batch_run", batch_run)
+    monkeypatch.setattr(serving.L, "lbm_batch_destroy", lambda b: None)
+
+
+def _trace():
+    return si.serving_trace(14, rate_per_s=2000.0, seed=11, L_lo=24, L_hi=60, steps_lo=35,
+                            steps_hi=300)
+
+
+def test_steps_of_rounds_up_to_the_quantum():
+    assert serving.steps_of({"steps": 2000}) == 2000
+    assert serving.steps_of({"steps": 2001}) == 2010
+    assert serving.steps_of({"steps": 1}) == serving.STEP_QUANTUM
+
+
+def test_contact_angle_map_passes_through_the_paper_points():
+    assert serving.g_ads_for_angle(90.0) == 0.0
+    assert serving.g_ads_for_angle(157.0) == pytest.approx(0.23)
+    assert serving.g_ads_for_angle(60.0) < 0.0 < serving.g_ads_for_angle(120.0)
+
+
+def test_request_params_use_the_coexistence_densities():
+    req = _trace()[0]
+    p, rv, rl = serving.request_params(req, "fp32")
+    assert p.nx == p.ny == p.nz == req["L"]
+    assert 0 < rv < rl and p.rho_ref == rv
+    assert p.bc[2][0] == p.bc[2][1] == L.LBM_BC_WALL
+    p64, _, _ = serving.request_params(req, "fp64")
+    assert p64.rho_ref == 0.0
+
+
+@pytest.mark.parametrize("budget_factor,max_slots", [(1.5, 64), (100.0, 3)])
+def test_batched_loop_completes_every_request_within_budget(monkeypatch, budget_factor, max_slots):
+    rec = Recorder()
+    install_fakes(monkeypatch, rec)
+    trace = _trace()
+    fps = [L.lbm_footprint_bytes(serving.request_params(r, "fp32")[0]) for r in trace]
+    budget = int(budget_factor * max(fps))
+    out = serving.serve(trace, "batched", "fp32", budget_bytes=budget, max_slots=max_slots,
+                        chunk=40, time_scale=1.0)
+    assert out["requests"] == len(trace)
+    assert sorted(r["id"] for r in out["records"]) == [r["id"] for r in trace]
+    # every lattice took exactly its request's (rounded) step count and was freed
+    assert not rec.alive
+    assert sorted(rec.closed.values()) == sorted(serving.steps_of(r) for r in trace)
+    assert rec.peak_bytes <= budget
+    assert rec.peak_alive <= max_slots + 2       # retiring lattices are freed one chunk later
+    assert all(r["latency"] >= 0 for r in out["records"])
+
+
+def test_sequential_loop_runs_one_request_at_a_time_in_arrival_order(monkeypatch):
+    rec = Recorder()
+    install_fakes(monkeypatch, rec)
+    trace = _trace()
+    out = serving.serve(trace, "sequential", "fp64", chunk=40)
+    assert out["requests"] == len(trace)
+    # the steps of each lattice form one contiguous run: no interleaving of requests
+    runs = [c for i, c in enumerate(rec.log) if i == 0 or rec.log[i - 1] != c]
+    assert len(runs) == len(set(runs)) == len(trace)
+    done = [r["id"] for r in sorted(out["records"], key=lambda r: r["t_done"])]
+    assert done == [r["id"] for r in sorted(trace, key=lambda r: r["t_arrival"])]
+    assert sorted(rec.closed.values()) == sorted(serving.steps_of(r) for r in trace)
