@@ -873,7 +873,9 @@ extern "C" lbm_status lbm_liquid_stats(lbm_ctx* c, double threshold, double rho_
 // ---------------------------------------------------------------------------------------
 // Batched stepping of many contexts: one launch per step over every member's tiles
 // (k_step_fused_batch), steps_per_launch launches captured once into a HIP graph.
-constexpr int kBatchTX = 64, kBatchTY = 4, kBatchZC = 16;
+// Tile shapes of the batched kernel (index lbm_batch::tile) and the z-chunk depth.
+constexpr int kBatchTiles[2][2] = {{64, 4}, {32, 8}};
+constexpr int kBatchZC = 16;
 
 struct lbm_batch {
     std::vector<lbm_ctx*> ctx;
@@ -886,6 +888,7 @@ struct lbm_batch {
     bool ran = false;
     long long blocks = 0;
     int geom = GEOM_WALLS;                // GEOM_MASK if any member has a cylinder
+    int tile = 0;                         // index into kBatchTiles
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
@@ -906,14 +909,39 @@ static lbm_status batch_fail(lbm_status s, const char* fmt, ...) {
     return batch_fail(e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "%s failed: %s",  \
                       #call, hipGetErrorString(e_)); } while (0)
 
+template <typename T, int TX, int TY>
+static void launch_batch(const lbm_batch* b, hipStream_t s, const void* table, bool pf) {
+    const dim3 grid((unsigned)b->blocks), block(TX * TY);
+    const DomainDesc<T>* tb = (const DomainDesc<T>*)table;
+    const int nd = (int)b->ctx.size();
+    if constexpr (sizeof(T) == 4) {
+        if (pf) {
+            if (b->geom == GEOM_MASK)
+                hipLaunchKernelGGL((k_step_fused_batch_pf<19, T, GEOM_MASK, TX, TY>), grid, block,
+                                   0, s, tb, nd);
+            else
+                hipLaunchKernelGGL((k_step_fused_batch_pf<19, T, GEOM_WALLS, TX, TY>), grid, block,
+                                   0, s, tb, nd);
+            return;
+        }
+    }
+    if (b->geom == GEOM_MASK)
+        hipLaunchKernelGGL((k_step_fused_batch<19, T, GEOM_MASK, TX, TY>), grid, block, 0, s, tb, nd);
+    else
+        hipLaunchKernelGGL((k_step_fused_batch<19, T, GEOM_WALLS, TX, TY>), grid, block, 0, s, tb, nd);
+}
+
 template <typename T>
 static lbm_status build_tables(lbm_batch* b) {
     using R = typename Arith<T>::type;
     std::vector<DomainDesc<T>> t[2];
     long long block0 = 0;
+    const int TX = kBatchTiles[b->tile][0], TY = kBatchTiles[b->tile][1];
     for (lbm_ctx* c : b->ctx) {
-        const int ntx = (c->p.nx + kBatchTX - 1) / kBatchTX, nty = (c->p.ny + kBatchTY - 1) / kBatchTY;
-        const int zc = std::min(kBatchZC, c->p.nz);
+        const int ntx = (c->p.nx + TX - 1) / TX, nty = (c->p.ny + TY - 1) / TY;
+        int zc = kBatchZC;
+        if (const char* e = getenv("LBM_BATCH_ZC")) zc = std::max(1, atoi(e));    // tuning override
+        zc = std::min(zc, c->p.nz);
         const long long nb = (long long)ntx * nty * ((c->p.nz + zc - 1) / zc);
         const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
                                                              ? (const void*)&c->pd : (const void*)&c->pf);
@@ -944,16 +972,14 @@ static lbm_status build_tables(lbm_batch* b) {
     BCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipError_t ce = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (ce != hipSuccess) { (void)hipStreamDestroy(cap); BCHK(ce); }
+    // Plain tiles: on serving mixes of box sizes (rows not 128-byte aligned) they beat the
+    // prefetching tiles (19.2 vs 17.9 GLUPS) and 32x8 tiles (16.2); LBM_BATCH_PF=1 selects
+    // the prefetching tiles for 4-byte storage (tuning).
+    bool pf = false;
+    if (const char* e = getenv("LBM_BATCH_PF")) pf = sizeof(T) == 4 && atoi(e) != 0;
     for (int s = 0; s < b->steps_per_launch; ++s) {
-        const DomainDesc<T>* tb = (const DomainDesc<T>*)b->table[s & 1];
-        if (b->geom == GEOM_MASK)
-            hipLaunchKernelGGL((k_step_fused_batch<19, T, GEOM_MASK, kBatchTX, kBatchTY>),
-                               dim3((unsigned)b->blocks), dim3(kBatchTX * kBatchTY), 0, cap,
-                               tb, (int)b->ctx.size());
-        else
-            hipLaunchKernelGGL((k_step_fused_batch<19, T, GEOM_WALLS, kBatchTX, kBatchTY>),
-                               dim3((unsigned)b->blocks), dim3(kBatchTX * kBatchTY), 0, cap,
-                               tb, (int)b->ctx.size());
+        if (b->tile == 0) launch_batch<T, kBatchTiles[0][0], kBatchTiles[0][1]>(b, cap, b->table[s & 1], pf);
+        else launch_batch<T, kBatchTiles[1][0], kBatchTiles[1][1]>(b, cap, b->table[s & 1], pf);
     }
     ce = hipStreamEndCapture(cap, &b->graph);
     (void)hipStreamDestroy(cap);
@@ -1004,6 +1030,7 @@ extern "C" lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, int32_t 
     b->storage = storage;
     for (int i = 0; i < n; ++i)
         if (ctxs[i]->p.cylinder && ctxs[i]->any_solid) b->geom = GEOM_MASK;
+    if (const char* e = getenv("LBM_BATCH_TILE")) b->tile = atoi(e) == 1 ? 1 : 0;   // tuning override
     auto bail = [&](lbm_status s) { batch_free(b); delete b; return s; };
     hipError_t e = hipSetDevice(ctxs[0]->device);
     if (e == hipSuccess) {

@@ -51,9 +51,10 @@ constexpr FusedCfg kFusedCfgs[] = {{32, 8, false, false}, {256, 2, true, false},
 constexpr int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
 constexpr int kFusedZcFullRow = 64, kFusedZcTiled = 16;
 
-// LDS bytes of k_step_fused_pf: psi ring, own-plane and halo-row population buffers.
-constexpr int fused_pf_lds_bytes(int Q, int tx, int ty) {
-    return 4 * (4 * (ty + 2) * tx + Q * tx * ty + Q * 2 * tx);
+// LDS bytes of a prefetching tile: psi ring, own-plane and halo population buffers.
+constexpr int fused_pf_lds_bytes(int Q, int tx, int ty, bool fullx = true) {
+    return fullx ? 4 * (4 * (ty + 2) * tx + Q * tx * ty + Q * 2 * tx)
+                 : 4 * (4 * (ty + 2) * (tx + 2) + Q * tx * ty + Q * (2 * (tx + ty) + 4));
 }
 constexpr int kLdsBytesPerCU = 160 * 1024;
 
@@ -327,40 +328,57 @@ __device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F);
 // for the loads in flight); the ring slot written at plane z+1 was last read at plane z-1,
 // one barrier earlier. The arithmetic per node is the one of fused_tile (same functions,
 // same order), so both give bitwise identical results.
-template <int Q, typename T, int GEOM, int TX, int TY>
+template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX>
 __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __restrict__ fout,
                                               const uint8_t* __restrict__ solid, const Grid& g,
-                                              const Phys<float>& P, int t, int zc, int hints) {
+                                              const Phys<float>& P, int t, int ntx, int nty,
+                                              int zc, int hints) {
     static_assert(sizeof(T) == 4, "the LDS prefetch moves 4-byte elements");
     using R = float;
-    constexpr int NT = TX * TY, H = 2 * TX;
-    static_assert(H % 64 == 0 && H <= NT && TX % 64 == 0, "rows must be whole wavefronts");
-    static_assert(fused_pf_lds_bytes(Q, TX, TY) <= kLdsBytesPerCU, "tile does not fit in LDS");
-    __shared__ R ring[4][TY + 2][TX];
+    constexpr int NT = TX * TY;
+    constexpr int LX = FULLX ? TX : TX + 2;
+    constexpr int OX = FULLX ? 0 : 1;                 // LDS column of tile column 0
+    constexpr int H = FULLX ? 2 * TX : 2 * (TX + TY) + 4;
+    static_assert(H <= NT && (!FULLX || TX % 64 == 0),
+                  "halo larger than the tile, or full rows not whole wavefronts");
+    static_assert(fused_pf_lds_bytes(Q, TX, TY, FULLX) <= kLdsBytesPerCU, "tile does not fit in LDS");
+    __shared__ R ring[4][TY + 2][LX];
     __shared__ T pf_own[Q][NT];
+    // the halo buffer holds H cells; the DMA of the last, partly used wavefront writes only
+    // its active lanes
     __shared__ T pf_halo[Q][H];
 
-    const int iy = t % ((g.ny + TY - 1) / TY);
-    const int iz = t / ((g.ny + TY - 1) / TY);
-    const int y0 = iy * TY, z0 = iz * zc;
+    const int ix = t % ntx; t /= ntx;
+    const int iy = t % nty;
+    const int iz = t / nty;
+    const int x0 = ix * TX, y0 = iy * TY, z0 = iz * zc;
     const int z1 = min(z0 + zc, g.nz);
     const int tid = threadIdx.x, wave = tid >> 6;
     const int lx = tid % TX, ly = tid / TX;
-    const int x = lx, y = y0 + ly;
-    const bool active = y < g.ny;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool active = x < g.nx && y < g.ny;
     auto wrapc = [](int c, int n) { c %= n; return c < 0 ? c + n : c; };
     const int nxy = g.nx * g.ny;
     const unsigned pst = (unsigned)g.stride * (unsigned)sizeof(T);
 
+    // halo cell of this thread (if any), as tile coordinates (hx, hy)
+    int hx = 0, hy = 0;
     const bool has_halo = tid < H;
-    const int hx = tid % TX, hy = tid < TX ? -1 : TY;
+    if (has_halo) {
+        if (FULLX) { hx = tid % TX; hy = tid < TX ? -1 : TY; }
+        else if (tid < LX) { hx = tid - 1; hy = -1; }
+        else if (tid < 2 * LX) { hx = tid - LX - 1; hy = TY; }
+        else if (tid < 2 * LX + TY) { hx = -1; hy = tid - 2 * LX; }
+        else { hx = TX; hy = tid - 2 * LX - TY; }
+    }
     int oxy[9], hxy[9];
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
             oxy[(dy + 1) * 3 + dx + 1] = wrapc(x + dx, g.nx) + wrapc(y + dy, g.ny) * g.nx;
-            hxy[(dy + 1) * 3 + dx + 1] = wrapc(hx + dx, g.nx) + wrapc(y0 + hy + dy, g.ny) * g.nx;
+            hxy[(dy + 1) * 3 + dx + 1] =
+                wrapc(x0 + hx + dx, g.nx) + wrapc(y0 + hy + dy, g.ny) * g.nx;
         }
     auto zoffs = [&](int zp, int* zo) {
         zo[0] = wrapc(zp - 1, g.nz) * nxy;
@@ -369,16 +387,18 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
     };
     WallBits wo{0u, 0u, 0u}, wh{0u, 0u, 0u};
     if (GEOM == GEOM_WALLS) {
-        wo.wx = wall_bits(x, g.nx, g.walls, 0);
+        wo.wx = wall_bits(wrapc(x, g.nx), g.nx, g.walls, 0);
         wo.wy = wall_bits(wrapc(y, g.ny), g.ny, g.walls, 1);
-        wh.wx = wall_bits(hx, g.nx, g.walls, 0);
+        wh.wx = wall_bits(wrapc(x0 + hx, g.nx), g.nx, g.walls, 0);
         wh.wy = wall_bits(wrapc(y0 + hy, g.ny), g.ny, g.walls, 1);
     }
     auto zbits = [&](int zp) {
         return GEOM == GEOM_WALLS ? wall_bits(wrapc(zp, g.nz), g.nz, g.walls, 2) : 0u;
     };
     auto psi_of = [&](R drho) { return pseudopotential<R>(P.rho_ref + drho, P); };
+    // LDS column of tile column lx + dx
     auto col = [&](int dx) {
+        if (!FULLX) return lx + 1 + dx;
         const int c = lx + dx;
         return c < 0 ? c + TX : (c >= TX ? c - TX : c);
     };
@@ -390,7 +410,7 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
         const WallBits wb{wo.wx, wo.wy, zbits(zp)};
         const bool s = node_solid<GEOM>(solid, oxy[4] + zo[1], wb);
         pull_loads<Q, T, R, GEOM>(fin, solid, oxy, zo, wb, pst, v);
-        ring[slot][ly + 1][lx] = s ? R(-1) : psi_of(sum_q<Q, R>(v));
+        ring[slot][ly + 1][lx + OX] = s ? R(-1) : psi_of(sum_q<Q, R>(v));
     };
     auto halo_psi = [&](int zp, int slot) {
         if (!has_halo) return;
@@ -404,12 +424,13 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
             pull_loads<Q, T, R, GEOM>(fin, solid, hxy, zo, wb, pst, v);
             hv = psi_of(sum_q<Q, R>(v));
         }
-        ring[slot][hy + 1][hx] = hv;
+        ring[slot][hy + 1][hx + OX] = hv;
     };
     // asynchronous pulls of plane zp into the LDS buffers (own node, halo node)
-    // Own pulls of the interior rows are read by no other tile (kHintNtInterior). A
-    // wavefront covers part of one row (TX is a multiple of 64), so the choice is uniform.
-    const bool interior_row = (hints & kHintNtInterior) && ly != 0 && ly != TY - 1;
+    // Own pulls of the interior rows of a full-row tile are read by no other tile
+    // (kHintNtInterior). A wavefront covers part of one row (TX is a multiple of 64), so
+    // the choice is uniform.
+    const bool interior_row = FULLX && (hints & kHintNtInterior) && ly != 0 && ly != TY - 1;
     auto prefetch_own = [&](int zp) {
         int zo[3];
         zoffs(zp, zo);
@@ -462,7 +483,7 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
             for (int i = 0; i < Q; ++i) s += static_cast<R>(pf_halo[i][tid]);
             hv = psi_of(s);
         }
-        ring[slot][hy + 1][hx] = hv;
+        ring[slot][hy + 1][hx + OX] = hv;
     };
     auto take_own = [&](int zp, int slot, R* v) {
         int zo[3];
@@ -470,7 +491,7 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
         const WallBits wb{wo.wx, wo.wy, zbits(zp)};
 #pragma unroll
         for (int i = 0; i < Q; ++i) v[i] = static_cast<R>(pf_own[i][tid]);
-        ring[slot][ly + 1][lx] =
+        ring[slot][ly + 1][lx + OX] =
             node_solid<GEOM>(solid, oxy[4] + zo[1], wb) ? R(-1) : psi_of(sum_q<Q, R>(v));
     };
 
@@ -494,7 +515,7 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
         wait_lds();
         if (more) prefetch_own(z + 2);
         barrier_lds();
-        const R psi0 = ring[s1][ly + 1][lx];
+        const R psi0 = ring[s1][ly + 1][lx + OX];
         if (active && !(psi0 < R(0))) {
             R pn[Q];
 #pragma unroll
@@ -527,7 +548,8 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_pf(const T* __restrict__
                                                           Grid g, Phys<float> P, int zc,
                                                           int remap, int hints) {
     const int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    fused_tile_pf<Q, T, GEOM, TX, TY>(fin, fout, solid, g, P, t, zc, hints);
+    fused_tile_pf<Q, T, GEOM, TX, TY, true>(fin, fout, solid, g, P, t, 1,
+                                            (g.ny + TY - 1) / TY, zc, hints);
 }
 
 // Single domain. remap != 0: map workgroups to tiles so that each XCD gets a contiguous
@@ -569,6 +591,21 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_batch(const DomainDesc<T
     const DomainDesc<T>& D = d[lo];
     fused_tile<Q, T, GEOM, TX, TY, false>(D.fin, D.fout, D.solid, D.g, D.P, b - D.block0,
                                                 D.ntx, D.nty, D.zc, kHintNtStore);
+}
+
+// Batched step with prefetching tiles (4-byte storage): as k_step_fused_batch.
+template <int Q, typename T, int GEOM, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void k_step_fused_batch_pf(const DomainDesc<T>* __restrict__ d,
+                                                                int ndom) {
+    const int b = blockIdx.x;
+    int lo = 0, hi = ndom - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].block0 <= b) lo = mid; else hi = mid - 1;
+    }
+    const DomainDesc<T>& D = d[lo];
+    fused_tile_pf<Q, T, GEOM, TX, TY, false>(D.fin, D.fout, D.solid, D.g, D.P, b - D.block0,
+                                             D.ntx, D.nty, D.zc, kHintNtStore);
 }
 
 }  // namespace lbmk

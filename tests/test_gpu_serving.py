@@ -36,8 +36,15 @@ def _make(L, w, storage):
     return lat
 
 
+@pytest.mark.parametrize("variant", ["plain", "prefetch", "tiles32x8"])
 @pytest.mark.parametrize("storage", ["fp32", "fp64"])
-def test_batch_equals_individual_steps(L, storage):
+def test_batch_equals_individual_steps(L, monkeypatch, storage, variant):
+    """Batched launches (default plain 64x4 tiles, prefetching tiles, 32x8 tiles) give each
+    member exactly the populations of its own single-lattice steps."""
+    if variant == "prefetch":
+        monkeypatch.setenv("LBM_BATCH_PF", "1")
+    if variant == "tiles32x8":
+        monkeypatch.setenv("LBM_BATCH_TILE", "1")
     ws = _members()
     alone = [_make(L, w, storage) for w in ws]
     mixed = [_make(L, w, storage) for w in ws]
