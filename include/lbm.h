@@ -167,6 +167,12 @@ lbm_status lbm_liquid_stats(lbm_ctx* c, double threshold, double rho_v, double r
 lbm_status lbm_kernel_times(lbm_ctx* c, int64_t nsteps, double* avg_ms, const char** names,
                             int32_t cap, int32_t* count);
 
+/* Measurement aid: attainable HBM bandwidth of a plain streaming copy on the current
+   device (bytes read + bytes written per second, in GB/s), the practical ceiling for the
+   step kernels. Allocates two buffers of `bytes` (>= 16 KiB) for the duration of the call,
+   times `reps` copies with HIP events on a private stream. Synchronous.                 */
+lbm_status lbm_copy_bandwidth(int64_t bytes, int32_t reps, double* gbs);
+
 /* Wait for all work enqueued on the context stream.                                   */
 lbm_status lbm_synchronize(lbm_ctx* c);
 

@@ -870,6 +870,40 @@ extern "C" lbm_status lbm_liquid_stats(lbm_ctx* c, double threshold, double rho_
     return poll_health(c, true);
 }
 
+extern "C" lbm_status lbm_copy_bandwidth(int64_t bytes, int32_t reps, double* gbs) {
+    if (!gbs || bytes < 16 * 1024 || reps < 1) return LBM_EINVAL;
+    const long long n = bytes / 16;
+    void *a = nullptr, *b = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    lbm_status st = LBM_OK;
+    auto ok = [&](hipError_t e) {
+        if (e != hipSuccess && st == LBM_OK) st = e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE;
+        return st == LBM_OK;
+    };
+    if (ok(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) && ok(hipMalloc(&a, n * 16)) &&
+        ok(hipMalloc(&b, n * 16)) && ok(hipMemsetAsync(a, 0, n * 16, s)) &&
+        ok(hipEventCreate(&e0)) && ok(hipEventCreate(&e1))) {
+        const dim3 grid(1024), block(256);      // 4 waves per CU slot: the best of a sweep
+        hipLaunchKernelGGL(k_copy_stream, grid, block, 0, s, (const lbm_f4*)a, (lbm_f4*)b, n);
+        if (ok(hipGetLastError()) && ok(hipEventRecord(e0, s))) {
+            for (int r = 0; r < reps; ++r)
+                hipLaunchKernelGGL(k_copy_stream, grid, block, 0, s, (const lbm_f4*)a, (lbm_f4*)b, n);
+            float ms = 0;
+            if (ok(hipGetLastError()) && ok(hipEventRecord(e1, s)) && ok(hipEventSynchronize(e1)) &&
+                ok(hipEventElapsedTime(&ms, e0, e1)))
+                *gbs = 2.0 * 16.0 * (double)n * reps / (ms * 1e-3) / 1e9;
+        }
+    }
+    if (s) (void)hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    if (s) (void)hipStreamDestroy(s);
+    return st;
+}
+
 // ---------------------------------------------------------------------------------------
 // Batched stepping of many contexts: one launch per step over every member's tiles
 // (k_step_fused_batch), steps_per_launch launches captured once into a HIP graph.

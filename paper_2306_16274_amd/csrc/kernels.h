@@ -395,6 +395,16 @@ __global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ in,
     if (threadIdx.x < C) out[(long long)blockIdx.x * C + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Plain streaming copy (measurement aid: the attainable read + write HBM bandwidth against
+// which the step kernels are judged): 16-byte elements, grid-stride, nontemporal hints.
+typedef float lbm_f4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy_stream(const lbm_f4* __restrict__ a,
+                                                     lbm_f4* __restrict__ b, long long n) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(a + i), b + i);
+}
+
 // Solid mask: wall layers on the faces set in g.walls and nodes whose centre lies in the
 // x-aligned cylinder (y - cy)^2 + (z - cz)^2 <= r^2 (float64, as on the host).
 __global__ __launch_bounds__(256) void k_build_solid(uint8_t* __restrict__ solid, Grid g, int cylinder,

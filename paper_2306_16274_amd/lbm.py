@@ -77,6 +77,7 @@ _SIGS = {
     "lbm_moments": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "lbm_liquid_stats": (ctypes.c_int, [_P, _D, _D, _D, ctypes.c_int32, _P, _P, _P]),
     "lbm_synchronize": (ctypes.c_int, [_P]),
+    "lbm_copy_bandwidth": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(_D)]),
     "lbm_kernel_times": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, ctypes.c_int32, _P]),
     "lbm_coexistence": (ctypes.c_int, [ctypes.POINTER(lbm_params), ctypes.POINTER(_D),
                                        ctypes.POINTER(_D)]),
@@ -192,6 +193,13 @@ def lbm_liquid_stats(ctx, nz, threshold, rho_v, rho_l, reach=1):
     _check(library().lbm_liquid_stats(ctx, threshold, rho_v, rho_l, reach, _ptr(cz), _ptr(wz),
                                       ctypes.byref(vol)), ctx)
     return cz, wz, float(vol.value)
+
+
+def lbm_copy_bandwidth(nbytes=2 << 30, reps=20):
+    """GB/s (read + write) of the library's streaming copy on the current device."""
+    v = ctypes.c_double(0.0)
+    _check(library().lbm_copy_bandwidth(nbytes, reps, ctypes.byref(v)))
+    return float(v.value)
 
 
 def lbm_kernel_times(ctx, nsteps, cap=8):
