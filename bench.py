@@ -7,8 +7,8 @@ static droplet (Carnahan-Starling EOS at T = 0.5 T_c, paper relaxation rates, +-
 interface noise), populations resident in HBM before timing starts.
 
 Prints one JSON line (rank 0): the FP32 shifted-storage throughput in MLUPS as `value`,
-the FP64 throughput beside it, the HBM roofline of the dominant kernel measured with HIP
-events on the launch stream, and the CPU oracle timed on a bounded sample.
+the FP64 and FP16-shifted throughputs beside it, the HBM roofline of the dominant kernel
+measured with HIP events on the launch stream, and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import hashlib
@@ -161,6 +161,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--fp64-steps", type=int, default=100)
+    ap.add_argument("--fp16-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rho-ref", default="vapour", choices=["zero", "vapour", "liquid"])
     ap.add_argument("--step-kernel", default="fused", choices=["fused", "two_pass"])
@@ -183,6 +184,7 @@ def main():
 
     r32 = run_gpu(w, "fp32", args.steps, args.warmup, args.rho_ref, args.step_kernel)
     r64 = run_gpu(w, "fp64", args.fp64_steps, max(2, args.warmup // 4), "zero", args.step_kernel)
+    r16 = run_gpu(w, "fp16", args.fp16_steps, max(2, args.warmup // 4), args.rho_ref, args.step_kernel)
     copy_gbs = copy_bandwidth()
     stream_copy_gbs = L.lbm_copy_bandwidth()
 
@@ -198,6 +200,7 @@ def main():
     step_bytes = 2 * Q * b * w.nodes                  # method minimum per step
     effective = step_bytes / (r32["ms_per_step"] * 1e-3) / 1e9
     eff64 = 2 * Q * 8 * w.nodes / (r64["ms_per_step"] * 1e-3) / 1e9
+    eff16 = 2 * Q * 2 * w.nodes / (r16["ms_per_step"] * 1e-3) / 1e9
 
     out = {
         "metric": "MLUPS, D3Q19 multiphase 256^3, FP32 shifted storage (FP64 beside it)",
@@ -222,6 +225,11 @@ def main():
                  "effective_GBs": round(eff64, 1),
                  "effective_frac": round(eff64 / HBM_PEAK_GBS, 4),
                  "kernel_ms": r64["kernel_ms"]},
+        "fp16": {"value": round(r16["mlups"], 1), "unit": "MLUPS",
+                 "ms_per_step": round(r16["ms_per_step"], 4), "steps": args.fp16_steps,
+                 "storage": "fp16 shifted", "effective_GBs": round(eff16, 1),
+                 "effective_frac": round(eff16 / HBM_PEAK_GBS, 4),
+                 "kernel_ms": r16["kernel_ms"]},
         "effective_step_GBs": round(effective, 1),
         "effective_step_frac": round(effective / HBM_PEAK_GBS, 4),
         "kernel_ms": r32["kernel_ms"],

@@ -526,11 +526,11 @@ static void launch_fused_cfg(lbm_ctx* c, const void* fin, void* fout) {
     }
 }
 
-// Full-row tiles with the LDS prefetch (k_step_fused_pf): only for 4-byte storage and a
-// lattice whose tile buffers fit in LDS; other combinations never select it.
+// Full-row tiles with the LDS prefetch (k_step_fused_pf): only for 2- and 4-byte storage and
+// a lattice whose tile buffers fit in LDS; other combinations run the plain full-row tiles.
 template <int Q, typename T, int TX, int TY>
 static void launch_fused_pf(lbm_ctx* c, const void* fin, void* fout) {
-    if constexpr (sizeof(T) == 4 && fused_pf_lds_bytes(Q, TX, TY) <= kLdsBytesPerCU) {
+    if constexpr ((sizeof(T) == 4 || sizeof(T) == 2) && fused_pf_lds_bytes(Q, TX, TY) <= kLdsBytesPerCU) {
         const int nty = (c->p.ny + TY - 1) / TY;
         int zc, remap, hints;
         fused_chunking(c, zc, remap, hints);

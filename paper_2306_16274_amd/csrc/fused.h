@@ -40,8 +40,8 @@ constexpr int kHintNtStore = 1, kHintNtInterior = 2;
 
 // Launch configurations of the fused step: tile width and height, whether the tile spans
 // the whole x row (then nx must equal tx), and pf: the next planes are prefetched into LDS
-// (k_step_fused_pf; 4-byte storage, and the populations of a tile plus its halo rows must fit
-// in LDS). 32x8 tiles serve widths other than 256. Full-row tiles march through 64-plane
+// (k_step_fused_pf; 2- or 4-byte storage, and the populations of a tile plus its halo rows
+// must fit in LDS). 32x8 tiles serve widths other than 256. Full-row tiles march through 64-plane
 // z-chunks, in dispatch order without the prefetch and in XCD-contiguous order with it;
 // small tiles through 16-plane chunks in XCD-contiguous order.
 struct FusedCfg { int tx, ty; bool fullx, pf; };
@@ -69,13 +69,14 @@ constexpr int default_fused_hints(const FusedCfg& c, int elem_bytes) {
 //     plain), else prefetching 256x2 tiles (D3Q27: 0.800 vs 0.926 plain 256x2, 1.142 plain
 //     256x4, which spills);
 //   8-byte storage: plain 256x2 tiles (256x4 spills; D3Q27 2.52 vs 4.10);
-//   2-byte storage: plain 256x4 for D3Q19 (0.34 vs 0.38), plain 256x2 for D3Q27 (0.64 vs 0.92).
+//   2-byte storage: prefetching 256x4 for D3Q19 (0.320 vs 0.342 plain), plain 256x2 for
+//     D3Q27 (0.630 vs 0.656 prefetching, 0.92 plain 256x4).
 constexpr int default_fused_cfg_index(int nx, int elem_bytes, int Q) {
     return nx != 256 ? 0
          : elem_bytes == 8 ? 1
          : elem_bytes == 4 ? (fused_pf_lds_bytes(Q, 256, 4) <= kLdsBytesPerCU ? 3
                               : fused_pf_lds_bytes(Q, 256, 2) <= kLdsBytesPerCU ? 4 : 1)
-         : (Q == 19 ? 2 : 1);
+         : (Q == 19 && fused_pf_lds_bytes(Q, 256, 4) <= kLdsBytesPerCU ? 3 : 1);
 }
 
 // Workgroup b -> tile index such that each XCD (b mod 8) gets a contiguous tile range.
@@ -328,13 +329,42 @@ __device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F);
 // for the loads in flight); the ring slot written at plane z+1 was last read at plane z-1,
 // one barrier earlier. The arithmetic per node is the one of fused_tile (same functions,
 // same order), so both give bitwise identical results.
+// Asynchronous load of one element per lane from global memory into LDS (the lane's element
+// lands at dst + 4 * lane); AUX selects the cache policy (0 default, 2 nontemporal).
+// (The builtin takes its size and policy as literal constants, hence one specialization each.)
+template <int SIZE, int AUX> __device__ __forceinline__ void lds_dma(const char* src, void* dst);
+template <> __device__ __forceinline__ void lds_dma<4, 0>(const char* src, void* dst) {
+    __builtin_amdgcn_global_load_lds(src, LBM_LDS_PTR(dst), 4, 0, 0);
+}
+template <> __device__ __forceinline__ void lds_dma<4, 2>(const char* src, void* dst) {
+    __builtin_amdgcn_global_load_lds(src, LBM_LDS_PTR(dst), 4, 0, 2);
+}
+template <> __device__ __forceinline__ void lds_dma<2, 0>(const char* src, void* dst) {
+    __builtin_amdgcn_global_load_lds(src, LBM_LDS_PTR(dst), 2, 0, 0);
+}
+template <> __device__ __forceinline__ void lds_dma<2, 2>(const char* src, void* dst) {
+    __builtin_amdgcn_global_load_lds(src, LBM_LDS_PTR(dst), 2, 0, 2);
+}
+
+// Prefetch slots: the LDS DMA writes each lane's element into a dword of its own (a 2-byte
+// element zero-extended into the low half), so 2-byte storage uses 4-byte slots.
+template <typename T> struct PfSlot { using type = T; };
+template <> struct PfSlot<_Float16> { using type = uint32_t; };
+template <typename T, typename R>
+__device__ __forceinline__ R pf_value(typename PfSlot<T>::type v) { return static_cast<R>(v); }
+template <>
+__device__ __forceinline__ float pf_value<_Float16, float>(uint32_t v) {
+    return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(v)));
+}
+
 template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX>
 __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __restrict__ fout,
                                               const uint8_t* __restrict__ solid, const Grid& g,
                                               const Phys<float>& P, int t, int ntx, int nty,
                                               int zc, int hints) {
-    static_assert(sizeof(T) == 4, "the LDS prefetch moves 4-byte elements");
+    static_assert(sizeof(T) == 4 || sizeof(T) == 2, "the LDS prefetch moves 2- or 4-byte elements");
     using R = float;
+    using S = typename PfSlot<T>::type;
     constexpr int NT = TX * TY;
     constexpr int LX = FULLX ? TX : TX + 2;
     constexpr int OX = FULLX ? 0 : 1;                 // LDS column of tile column 0
@@ -343,10 +373,10 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
                   "halo larger than the tile, or full rows not whole wavefronts");
     static_assert(fused_pf_lds_bytes(Q, TX, TY, FULLX) <= kLdsBytesPerCU, "tile does not fit in LDS");
     __shared__ R ring[4][TY + 2][LX];
-    __shared__ T pf_own[Q][NT];
+    __shared__ S pf_own[Q][NT];
     // the halo buffer holds H cells; the DMA of the last, partly used wavefront writes only
     // its active lanes
-    __shared__ T pf_halo[Q][H];
+    __shared__ S pf_halo[Q][H];
 
     const int ix = t % ntx; t /= ntx;
     const int iy = t % nty;
@@ -440,18 +470,18 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
             for (int i = 0; i < Q; ++i) {
                 int e, pop;
                 pull_source<Q, GEOM>(i, oxy, zo, solid, wb, e, pop);
-                __builtin_amdgcn_global_load_lds(
-                    reinterpret_cast<const char*>(fin) + ((unsigned)e * 4u + (unsigned)pop * pst),
-                    LBM_LDS_PTR(&pf_own[i][wave * 64]), 4, 0, 2);
+                lds_dma<(int)sizeof(T), 2>(
+                    reinterpret_cast<const char*>(fin) + ((unsigned)e * (unsigned)sizeof(T) + (unsigned)pop * pst),
+                    &pf_own[i][wave * 64]);
             }
         } else {
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 int e, pop;
                 pull_source<Q, GEOM>(i, oxy, zo, solid, wb, e, pop);
-                __builtin_amdgcn_global_load_lds(
-                    reinterpret_cast<const char*>(fin) + ((unsigned)e * 4u + (unsigned)pop * pst),
-                    LBM_LDS_PTR(&pf_own[i][wave * 64]), 4, 0, 0);
+                lds_dma<(int)sizeof(T), 0>(
+                    reinterpret_cast<const char*>(fin) + ((unsigned)e * (unsigned)sizeof(T) + (unsigned)pop * pst),
+                    &pf_own[i][wave * 64]);
             }
         }
     };
@@ -464,9 +494,9 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
         for (int i = 0; i < Q; ++i) {
             int e, pop;
             pull_source<Q, GEOM>(i, hxy, zo, solid, hb, e, pop);
-            __builtin_amdgcn_global_load_lds(
-                reinterpret_cast<const char*>(fin) + ((unsigned)e * 4u + (unsigned)pop * pst),
-                LBM_LDS_PTR(&pf_halo[i][wave * 64]), 4, 0, 0);
+            lds_dma<(int)sizeof(T), 0>(
+                reinterpret_cast<const char*>(fin) + ((unsigned)e * (unsigned)sizeof(T) + (unsigned)pop * pst),
+                &pf_halo[i][wave * 64]);
         }
     };
     // plane zp from the LDS buffers: psi of the halo node; own populations into v and psi
@@ -480,7 +510,7 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
         else {
             R s = 0;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) s += static_cast<R>(pf_halo[i][tid]);
+            for (int i = 0; i < Q; ++i) s += pf_value<T, R>(pf_halo[i][tid]);
             hv = psi_of(s);
         }
         ring[slot][hy + 1][hx + OX] = hv;
@@ -490,7 +520,7 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
         zoffs(zp, zo);
         const WallBits wb{wo.wx, wo.wy, zbits(zp)};
 #pragma unroll
-        for (int i = 0; i < Q; ++i) v[i] = static_cast<R>(pf_own[i][tid]);
+        for (int i = 0; i < Q; ++i) v[i] = pf_value<T, R>(pf_own[i][tid]);
         ring[slot][ly + 1][lx + OX] =
             node_solid<GEOM>(solid, oxy[4] + zo[1], wb) ? R(-1) : psi_of(sum_q<Q, R>(v));
     };

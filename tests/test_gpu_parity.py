@@ -257,9 +257,10 @@ def test_full_size_256_sampled_windows(L, storage):
     assert worst < (1e-12 if storage == "fp64" else 1e-6)
 
 
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
 @pytest.mark.parametrize("geom", ["periodic", "walls", "cylinder"])
 @pytest.mark.parametrize("Q", [19, 27])
-def test_fused_prefetch_tiles_bitwise_equal_plain_tiles(L, monkeypatch, geom, Q):
+def test_fused_prefetch_tiles_bitwise_equal_plain_tiles(L, monkeypatch, geom, Q, storage):
     """Full-row tiles with the LDS prefetch (launch configurations 3 = 256x4 and 4 = 256x2,
     the 256-wide FP32 defaults) against plain full-row tiles (2 = 256x4, 1 = 256x2) and the
     32x8 tiles (0): the per-node arithmetic is the same, so the populations agree bit for
@@ -276,7 +277,7 @@ def test_fused_prefetch_tiles_bitwise_equal_plain_tiles(L, monkeypatch, geom, Q)
     monkeypatch.setenv("LBM_FUSED_ZC", "7")
     for cfg in ("3", "4", "2", "1", "0"):
         monkeypatch.setenv("LBM_FUSED_CONFIG", cfg)
-        with L.Lattice(gpu_params(w, "fp32", rho_ref=rv)) as lat:
+        with L.Lattice(gpu_params(w, storage, rho_ref=rv)) as lat:
             lat.init_droplet(*w.droplet_centre(), w.R, w.W, rl, rv, *w.U, w.noise, w.seed)
             lat.step(12)
             out[cfg] = lat.get_populations()
