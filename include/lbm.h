@@ -95,8 +95,11 @@ typedef struct {
 lbm_status lbm_params_default(lbm_params* p);
 
 /* Validate *p, allocate the lattice on the current HIP device and return a context in
-   *out. Rejects: lattice not 19/27, sizes < 1, rates outside (0,2), nu <= 0, an EOS
-   without a two-phase region, a cylinder that covers the domain. The populations are
+   *out. Rejects (LBM_EINVAL, before any device call): lattice not 19/27, unknown storage,
+   EOS, boundary condition or step kernel, sizes < 1 or beyond the launch grid, G >= 0,
+   non-positive EOS constants, rates outside (0,2), nu <= 0, non-finite parameters, a
+   cylinder radius <= 0, an EOS without a two-phase region, a geometry without fluid
+   nodes, a fused step on a population buffer of 4 GiB or more. The populations are
    undefined until one of the lbm_init_* / lbm_set_populations calls.                  */
 lbm_status lbm_create(const lbm_params* p, lbm_ctx** out);
 

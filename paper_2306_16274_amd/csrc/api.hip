@@ -247,7 +247,8 @@ static lbm_status validate(const lbm_params& p) {
     if (p.nx < 1 || p.ny < 1 || p.nz < 1) return fail(nullptr, LBM_EINVAL, "lattice sizes must be >= 1");
     const long long N = (long long)p.nx * p.ny * p.nz;
     if (N > 0x7fffffffLL) return fail(nullptr, LBM_EINVAL, "more than 2^31-1 nodes");
-    if (p.nz > 65535 || p.ny > 65535 * 4) return fail(nullptr, LBM_EINVAL, "nz above 65535");
+    if (p.nz > 65535 || p.ny > 65535 * 4)
+        return fail(nullptr, LBM_EINVAL, "nz above 65535 or ny above 262140 (launch grid limits)");
     if (p.eos != LBM_EOS_CS && p.eos != LBM_EOS_PIECEWISE) return fail(nullptr, LBM_EINVAL, "unknown eos");
     if (!(p.G < 0.0)) return fail(nullptr, LBM_EINVAL, "G must be negative (attractive)");
     if (p.eos == LBM_EOS_CS && !(p.cs_a > 0 && p.cs_b > 0 && p.cs_R > 0 && p.T_over_Tc > 0))
@@ -255,6 +256,11 @@ static lbm_status validate(const lbm_params& p) {
     if (p.eos == LBM_EOS_PIECEWISE &&
         !(p.pw_theta_v > 0 && p.pw_theta_l > 0 && p.pw_theta_m < 0 && p.pw_rho1 > 0 && p.pw_rho2 > p.pw_rho1))
         return fail(nullptr, LBM_EINVAL, "piecewise EOS needs theta_v, theta_l > 0 > theta_m and 0 < rho1 < rho2");
+    const double finite[] = {p.rho_ref, p.sigma, p.kappa, p.G_ads, p.G, p.body_force[0],
+                             p.body_force[1], p.body_force[2], p.cyl_y, p.cyl_z, p.cyl_r};
+    for (double v : finite)
+        if (!std::isfinite(v)) return fail(nullptr, LBM_EINVAL, "non-finite parameter value");
+    if (p.cylinder && !(p.cyl_r > 0)) return fail(nullptr, LBM_EINVAL, "cylinder radius must be positive");
     if (!(p.nu_l > 0) || !(p.nu_v > 0)) return fail(nullptr, LBM_EINVAL, "viscosities must be positive");
     if (p.nu_v != p.nu_l && !(p.rho_l != p.rho_v)) return fail(nullptr, LBM_EINVAL, "rho_l == rho_v with nu_l != nu_v");
     const double rates[] = {p.s2b, p.s3, p.s3b, p.s4, p.s4b, p.s5, p.s6, 1.0 / (3 * p.nu_l + 0.5),
@@ -373,6 +379,10 @@ extern "C" lbm_status lbm_create(const lbm_params* pp, lbm_ctx** out) {
         fail(c, e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "%s failed: %s", #call, \
              hipGetErrorString(e_));                                                      \
         return bail(e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE); } } while (0)
+    if (count_fluid(*pp, c->any_solid) == 0) {       // host-only: before any device call
+        fail(c, LBM_EINVAL, "geometry leaves no fluid node");
+        return bail(LBM_EINVAL);
+    }
     CHK(hipGetDevice(&c->device));
     if (pp->stream) c->stream = (hipStream_t)pp->stream;
     else { CHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)); c->own_stream = true; }
@@ -383,10 +393,6 @@ extern "C" lbm_status lbm_create(const lbm_params* pp, lbm_ctx** out) {
     CHK(hipMemsetAsync(c->f[1], 0, fbytes, c->stream));
     CHK(dmalloc(c->stream, &c->psi, (size_t)c->N * (pp->storage == LBM_FP64 ? 8 : 4)));
     CHK(dmalloc(c->stream, (void**)&c->solid, (size_t)c->N));
-    if (count_fluid(*pp, c->any_solid) == 0) {
-        fail(c, LBM_EINVAL, "geometry leaves no fluid node");
-        return bail(LBM_EINVAL);
-    }
     {
         const Launch L = node_launch(c);
         hipLaunchKernelGGL(k_build_solid, L.grid, L.block, 0, c->stream, c->solid, grid_of(c),

@@ -82,3 +82,50 @@ def test_coexistence_agrees_with_oracle_maxwell():
     p.eos = lbm.LBM_EOS_PIECEWISE
     rv, rl = lbm.lbm_coexistence(p)
     assert abs(rv - 0.001) < 1e-8 and abs(rl - 1.0) < 1e-7
+
+
+def _bad(**changes):
+    from paper_2306_16274_amd import lbm
+    p = lbm.lbm_params_default()
+    for k, v in changes.items():
+        if k == "bc":
+            p.bc[0][1] = v
+        elif k == "body_force":
+            p.body_force[2] = v
+        else:
+            setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("changes,message", [
+    (dict(lattice=15), "lattice"),
+    (dict(storage=7), "storage"),
+    (dict(nx=0), "sizes"),
+    (dict(nz=70000), "grid"),
+    (dict(nx=2048, ny=2048, nz=1024), "2^31"),
+    (dict(eos=5), "eos"),
+    (dict(G=0.5), "G must be negative"),
+    (dict(cs_a=-1.0), "Carnahan"),
+    (dict(eos=1, pw_theta_m=0.1), "piecewise"),
+    (dict(nu_l=0.0), "viscosit"),
+    (dict(nu_l=-0.1), "viscosit"),
+    (dict(s4=2.5), "relaxation rate"),
+    (dict(s2b=0.0), "relaxation rate"),
+    (dict(sigma=float("nan")), "non-finite"),
+    (dict(body_force=float("inf")), "non-finite"),
+    (dict(cylinder=1, cyl_r=0.0), "cylinder radius"),
+    (dict(cylinder=1, cyl_y=32.0, cyl_z=32.0, cyl_r=200.0), "no fluid"),
+    (dict(bc=3), "boundary"),
+    (dict(reduce_every=-1), "reduce_every"),
+    (dict(step_kernel=9), "step_kernel"),
+    (dict(lattice=27, storage=0, nx=512, ny=512, nz=512), "4 GiB"),
+    (dict(T_over_Tc=1.2), "two-phase"),
+])
+def test_create_rejects_invalid_parameters_before_touching_the_device(changes, message):
+    """lbm_create validates on the host: every rejection is LBM_EINVAL with a message,
+    without a GPU."""
+    from paper_2306_16274_amd import lbm
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.lbm_create(_bad(**changes))
+    assert ei.value.status == lbm.LBM_EINVAL
+    assert message in str(ei.value), str(ei.value)
