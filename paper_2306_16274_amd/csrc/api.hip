@@ -532,11 +532,33 @@ static void launch_fused_cfg(lbm_ctx* c, const void* fin, void* fout) {
     }
 }
 
-// Full-row tiles with the LDS prefetch (k_step_fused_pf): only for 2- and 4-byte storage and
-// a lattice whose tile buffers fit in LDS; other combinations run the plain full-row tiles.
+// Full-row tiles with the LDS prefetch: k_step_fused_pf for 2- and 4-byte storage,
+// k_step_fused_pf64 (own populations only) for FP64, where the tile buffers fit in LDS; other
+// combinations run the plain full-row tiles.
 template <int Q, typename T, int TX, int TY>
 static void launch_fused_pf(lbm_ctx* c, const void* fin, void* fout) {
-    if constexpr ((sizeof(T) == 4 || sizeof(T) == 2) && fused_pf_lds_bytes(Q, TX, TY) <= kLdsBytesPerCU) {
+    if constexpr (std::is_same<T, double>::value && fused_pf64_lds_bytes(Q, TX, TY) <= kLdsBytesPerCU) {
+        const int nty = (c->p.ny + TY - 1) / TY;
+        int zc, remap, hints;
+        fused_chunking(c, zc, remap, hints);
+        const int nchunks = (c->p.nz + zc - 1) / zc;
+        const dim3 grid((unsigned)(nty * nchunks)), block(TX * TY);
+        const double* f0 = (const double*)fin;
+        double* f1 = (double*)fout;
+        switch (geom_of(c)) {
+        case GEOM_NONE:
+            hipLaunchKernelGGL((k_step_fused_pf64<Q, GEOM_NONE, TX, TY>), grid, block, 0, c->stream,
+                               f0, f1, c->solid, grid_of(c), c->pd, zc, remap, hints);
+            break;
+        case GEOM_WALLS:
+            hipLaunchKernelGGL((k_step_fused_pf64<Q, GEOM_WALLS, TX, TY>), grid, block, 0, c->stream,
+                               f0, f1, c->solid, grid_of(c), c->pd, zc, remap, hints);
+            break;
+        default:
+            hipLaunchKernelGGL((k_step_fused_pf64<Q, GEOM_MASK, TX, TY>), grid, block, 0, c->stream,
+                               f0, f1, c->solid, grid_of(c), c->pd, zc, remap, hints);
+        }
+    } else if constexpr ((sizeof(T) == 4 || sizeof(T) == 2) && fused_pf_lds_bytes(Q, TX, TY) <= kLdsBytesPerCU) {
         const int nty = (c->p.ny + TY - 1) / TY;
         int zc, remap, hints;
         fused_chunking(c, zc, remap, hints);

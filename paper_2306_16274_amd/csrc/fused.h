@@ -57,6 +57,11 @@ constexpr int fused_pf_lds_bytes(int Q, int tx, int ty, bool fullx = true) {
                  : 4 * (4 * (ty + 2) * (tx + 2) + Q * tx * ty + Q * (2 * (tx + ty) + 4));
 }
 constexpr int kLdsBytesPerCU = 160 * 1024;
+// LDS bytes of an FP64 full-row tile with own-population prefetch: psi ring (8-byte) and the
+// two dword slot arrays of the own buffer.
+constexpr int fused_pf64_lds_bytes(int Q, int tx, int ty) {
+    return 4 * (ty + 2) * tx * 8 + 2 * Q * tx * ty * 4;
+}
 
 constexpr int default_fused_zc(const FusedCfg& c) { return c.fullx ? kFusedZcFullRow : kFusedZcTiled; }
 constexpr int default_fused_remap(const FusedCfg& c) { return (!c.fullx || c.pf) ? 1 : 0; }
@@ -68,12 +73,14 @@ constexpr int default_fused_hints(const FusedCfg& c, int elem_bytes) {
 //   4-byte storage: prefetching 256x4 tiles where they fit in LDS (D3Q19: 0.506 vs 0.536
 //     plain), else prefetching 256x2 tiles (D3Q27: 0.800 vs 0.926 plain 256x2, 1.142 plain
 //     256x4, which spills);
-//   8-byte storage: plain 256x2 tiles (256x4 spills; D3Q27 2.52 vs 4.10);
+//   8-byte storage: plain 256x2 tiles for D3Q19 (1.25 vs 1.31 with the own-population
+//     prefetch of k_step_fused_pf64; 256x4 spills), prefetching 256x2 for D3Q27 (2.36 vs
+//     2.56 plain, 4.10 plain 256x4);
 //   2-byte storage: prefetching 256x4 for D3Q19 (0.320 vs 0.342 plain), plain 256x2 for
 //     D3Q27 (0.630 vs 0.656 prefetching, 0.92 plain 256x4).
 constexpr int default_fused_cfg_index(int nx, int elem_bytes, int Q) {
     return nx != 256 ? 0
-         : elem_bytes == 8 ? 1
+         : elem_bytes == 8 ? (Q == 27 && fused_pf64_lds_bytes(Q, 256, 2) <= kLdsBytesPerCU ? 4 : 1)
          : elem_bytes == 4 ? (fused_pf_lds_bytes(Q, 256, 4) <= kLdsBytesPerCU ? 3
                               : fused_pf_lds_bytes(Q, 256, 2) <= kLdsBytesPerCU ? 4 : 1)
          : (Q == 19 && fused_pf_lds_bytes(Q, 256, 4) <= kLdsBytesPerCU ? 3 : 1);
@@ -569,6 +576,164 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
 #pragma unroll
         for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
     }
+}
+
+// FP64 full-row tile with the own populations of plane z+2 prefetched into LDS (each double
+// as two dword DMAs into a low and a high slot array). The halo rows are pulled
+// synchronously, before the prefetch is issued: vector memory completes in order, so waiting
+// for the halo loads after the prefetch would also wait for the prefetch. The own buffer
+// (77.8 KB at 256x2, D3Q19) and the psi ring (32 KB) fit in LDS; a halo buffer would not.
+// Arithmetic per node as in fused_tile (bitwise identical results).
+template <int Q, int GEOM, int TX, int TY>
+__device__ __forceinline__ void fused_tile_pf64(const double* __restrict__ fin,
+                                                double* __restrict__ fout,
+                                                const uint8_t* __restrict__ solid, const Grid& g,
+                                                const Phys<double>& P, int t, int nty, int zc,
+                                                int hints) {
+    using R = double;
+    using T = double;
+    constexpr int NT = TX * TY, H = 2 * TX;
+    static_assert(H <= NT && TX % 64 == 0, "full rows must be whole wavefronts");
+    static_assert(fused_pf64_lds_bytes(Q, TX, TY) <= kLdsBytesPerCU, "tile does not fit in LDS");
+    __shared__ R ring[4][TY + 2][TX];
+    __shared__ uint32_t pf_lo[Q][NT];
+    __shared__ uint32_t pf_hi[Q][NT];
+
+    const int iy = t % nty;
+    const int iz = t / nty;
+    const int y0 = iy * TY, z0 = iz * zc;
+    const int z1 = min(z0 + zc, g.nz);
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int lx = tid % TX, ly = tid / TX;
+    const int x = lx, y = y0 + ly;
+    const bool active = y < g.ny;
+    auto wrapc = [](int c, int n) { c %= n; return c < 0 ? c + n : c; };
+    const int nxy = g.nx * g.ny;
+    const unsigned pst = (unsigned)g.stride * (unsigned)sizeof(T);
+    const bool has_halo = tid < H;
+    const int hx = tid % TX, hy = tid < TX ? -1 : TY;
+    int oxy[9], hxy[9];
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            oxy[(dy + 1) * 3 + dx + 1] = wrapc(x + dx, g.nx) + wrapc(y + dy, g.ny) * g.nx;
+            hxy[(dy + 1) * 3 + dx + 1] = wrapc(hx + dx, g.nx) + wrapc(y0 + hy + dy, g.ny) * g.nx;
+        }
+    auto zoffs = [&](int zp, int* zo) {
+        zo[0] = wrapc(zp - 1, g.nz) * nxy;
+        zo[1] = wrapc(zp, g.nz) * nxy;
+        zo[2] = wrapc(zp + 1, g.nz) * nxy;
+    };
+    WallBits wo{0u, 0u, 0u}, wh{0u, 0u, 0u};
+    if (GEOM == GEOM_WALLS) {
+        wo.wx = wall_bits(x, g.nx, g.walls, 0);
+        wo.wy = wall_bits(wrapc(y, g.ny), g.ny, g.walls, 1);
+        wh.wx = wall_bits(hx, g.nx, g.walls, 0);
+        wh.wy = wall_bits(wrapc(y0 + hy, g.ny), g.ny, g.walls, 1);
+    }
+    auto zbits = [&](int zp) {
+        return GEOM == GEOM_WALLS ? wall_bits(wrapc(zp, g.nz), g.nz, g.walls, 2) : 0u;
+    };
+    auto psi_of = [&](R drho) { return pseudopotential<R>(P.rho_ref + drho, P); };
+    auto col = [&](int dx) {
+        const int c = lx + dx;
+        return c < 0 ? c + TX : (c >= TX ? c - TX : c);
+    };
+    auto own_psi = [&](int zp, int slot, R* v) {
+        int zo[3];
+        zoffs(zp, zo);
+        const WallBits wb{wo.wx, wo.wy, zbits(zp)};
+        const bool s = node_solid<GEOM>(solid, oxy[4] + zo[1], wb);
+        pull_loads<Q, T, R, GEOM>(fin, solid, oxy, zo, wb, pst, v);
+        ring[slot][ly + 1][lx] = s ? R(-1) : psi_of(sum_q<Q, R>(v));
+    };
+    auto halo_psi = [&](int zp, int slot) {
+        if (!has_halo) return;
+        int zo[3];
+        zoffs(zp, zo);
+        const WallBits wb{wh.wx, wh.wy, zbits(zp)};
+        R hv;
+        if (node_solid<GEOM>(solid, hxy[4] + zo[1], wb)) hv = R(-1);
+        else {
+            R v[Q];
+            pull_loads<Q, T, R, GEOM>(fin, solid, hxy, zo, wb, pst, v);
+            hv = psi_of(sum_q<Q, R>(v));
+        }
+        ring[slot][hy + 1][hx] = hv;
+    };
+    auto prefetch_own = [&](int zp) {
+        int zo[3];
+        zoffs(zp, zo);
+        const WallBits wb{wo.wx, wo.wy, zbits(zp)};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int e, pop;
+            pull_source<Q, GEOM>(i, oxy, zo, solid, wb, e, pop);
+            const char* src = reinterpret_cast<const char*>(fin) + ((unsigned)e * 8u + (unsigned)pop * pst);
+            lds_dma<4, 0>(src, &pf_lo[i][wave * 64]);
+            lds_dma<4, 0>(src + 4, &pf_hi[i][wave * 64]);
+        }
+    };
+    auto take_own = [&](int zp, int slot, R* v) {
+        int zo[3];
+        zoffs(zp, zo);
+        const WallBits wb{wo.wx, wo.wy, zbits(zp)};
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            v[i] = __builtin_bit_cast(double, ((unsigned long long)pf_hi[i][tid] << 32) | pf_lo[i][tid]);
+        ring[slot][ly + 1][lx] =
+            node_solid<GEOM>(solid, oxy[4] + zo[1], wb) ? R(-1) : psi_of(sum_q<Q, R>(v));
+    };
+
+    R cur[Q], nxt[Q];
+    own_psi(z0 - 1, 0, nxt);
+    halo_psi(z0 - 1, 0);
+    own_psi(z0, 1, cur);
+    halo_psi(z0, 1);
+    prefetch_own(z0 + 1);
+    for (int z = z0; z < z1; ++z) {
+        const int k = z - z0;
+        const int s0 = k & 3, s1 = (k + 1) & 3, s2 = (k + 2) & 3;
+        wait_vector_memory();
+        take_own(z + 1, s2, nxt);
+        halo_psi(z + 1, s2);
+        wait_lds();
+        if (z + 1 < z1) prefetch_own(z + 2);
+        barrier_lds();
+        const R psi0 = ring[s1][ly + 1][lx];
+        if (active && !(psi0 < R(0))) {
+            R pn[Q];
+#pragma unroll
+            for (int j = 0; j < Q; ++j) {
+                const int ez = vel_z(j);
+                const int sl = ez < 0 ? s0 : (ez > 0 ? s2 : s1);
+                pn[j] = ring[sl][ly + 1 + vel_y(j)][col(vel_x(j))];
+            }
+            const NodeForce<R> nf = node_force<Q, R>(psi0, pn, P);
+            collide<Q, R>(cur, nf, P);
+            const unsigned nb = (unsigned)(oxy[4] + z * nxy) * (unsigned)sizeof(T);
+            if (hints & kHintNtStore) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) st_off_nt(fout, nb + (unsigned)i * pst, cur[i]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) st_off(fout, nb + (unsigned)i * pst, cur[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
+    }
+}
+
+template <int Q, int GEOM, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void k_step_fused_pf64(const double* __restrict__ fin,
+                                                            double* __restrict__ fout,
+                                                            const uint8_t* __restrict__ solid,
+                                                            Grid g, Phys<double> P, int zc,
+                                                            int remap, int hints) {
+    const int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    fused_tile_pf64<Q, GEOM, TX, TY>(fin, fout, solid, g, P, t, (g.ny + TY - 1) / TY, zc, hints);
 }
 
 template <int Q, typename T, int GEOM, int TX, int TY>

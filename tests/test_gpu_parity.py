@@ -257,7 +257,7 @@ def test_full_size_256_sampled_windows(L, storage):
     assert worst < (1e-12 if storage == "fp64" else 1e-6)
 
 
-@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "fp64"])
 @pytest.mark.parametrize("geom", ["periodic", "walls", "cylinder"])
 @pytest.mark.parametrize("Q", [19, 27])
 def test_fused_prefetch_tiles_bitwise_equal_plain_tiles(L, monkeypatch, geom, Q, storage):
@@ -277,7 +277,8 @@ def test_fused_prefetch_tiles_bitwise_equal_plain_tiles(L, monkeypatch, geom, Q,
     monkeypatch.setenv("LBM_FUSED_ZC", "7")
     for cfg in ("3", "4", "2", "1", "0"):
         monkeypatch.setenv("LBM_FUSED_CONFIG", cfg)
-        with L.Lattice(gpu_params(w, storage, rho_ref=rv)) as lat:
+        ref = 0.0 if storage == "fp64" else rv
+        with L.Lattice(gpu_params(w, storage, rho_ref=ref)) as lat:
             lat.init_droplet(*w.droplet_centre(), w.R, w.W, rl, rv, *w.U, w.noise, w.seed)
             lat.step(12)
             out[cfg] = lat.get_populations()
