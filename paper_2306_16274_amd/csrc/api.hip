@@ -44,6 +44,7 @@ struct lbm_ctx {
     Phys<double> pd{};
     Phys<float> pf{};
     int fused_cfg = 0;             // index into kFusedCfgs
+    int cus = 256;                 // compute units of the device
     std::string err;
 };
 
@@ -384,6 +385,7 @@ extern "C" lbm_status lbm_create(const lbm_params* pp, lbm_ctx** out) {
         return bail(LBM_EINVAL);
     }
     CHK(hipGetDevice(&c->device));
+    CHK(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device));
     if (pp->stream) c->stream = (hipStream_t)pp->stream;
     else { CHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)); c->own_stream = true; }
     const size_t fbytes = (size_t)c->Q * c->stride * c->elem;
@@ -488,12 +490,12 @@ static int default_fused_cfg(const lbm_ctx* c) {
     return default_fused_cfg_index(c->p.nx, (int)c->elem, c->Q);
 }
 
-// Planes per z-chunk and tile order. Full-row tiles: 64-plane chunks (about one
-// workgroup per CU slot at 256^3), dispatch order left as is. Small tiles: 16-plane
-// chunks, XCD-contiguous tile ranges (neighbouring tiles then share an L2). Measured on
-// MI355X at 256^3 (D3Q19, FP32 and FP64).
+// Planes per z-chunk and tile order (defaults of fused.h: about one workgroup per CU for
+// full-row tiles, XCD-contiguous tile ranges so that neighbouring rows share an L2).
 static void fused_chunking(const lbm_ctx* c, int& zc, int& remap, int& hints) {
-    zc = default_fused_zc(kFusedCfgs[c->fused_cfg]);
+    const FusedCfg& f = kFusedCfgs[c->fused_cfg];
+    const long long tiles = (long long)((c->p.nx + f.tx - 1) / f.tx) * ((c->p.ny + f.ty - 1) / f.ty);
+    zc = default_fused_zc(f, tiles, c->p.nz, c->cus);
     remap = default_fused_remap(kFusedCfgs[c->fused_cfg]);
     hints = default_fused_hints(kFusedCfgs[c->fused_cfg], (int)c->elem);
     if (const char* e = getenv("LBM_FUSED_HINTS")) hints = atoi(e);            // tuning override

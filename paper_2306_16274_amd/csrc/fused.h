@@ -41,15 +41,17 @@ constexpr int kHintNtStore = 1, kHintNtInterior = 2;
 // Launch configurations of the fused step: tile width and height, whether the tile spans
 // the whole x row (then nx must equal tx), and pf: the next planes are prefetched into LDS
 // (k_step_fused_pf; 2- or 4-byte storage, and the populations of a tile plus its halo rows
-// must fit in LDS). 32x8 tiles serve widths other than 256. Full-row tiles march through 64-plane
-// z-chunks, in dispatch order without the prefetch and in XCD-contiguous order with it;
-// small tiles through 16-plane chunks in XCD-contiguous order.
+// must fit in LDS). 32x8 tiles serve widths other than 256. Full-row tiles cut z into as many
+// chunks as it takes for about one workgroup per CU (each holds a CU alone: LDS or VGPRs), so
+// every workgroup marches as far as possible and the two lead-in planes of a chunk are paid
+// rarely; small tiles march through 16-plane chunks. Both map tiles to XCDs in contiguous
+// ranges.
 struct FusedCfg { int tx, ty; bool fullx, pf; };
 constexpr FusedCfg kFusedCfgs[] = {{32, 8, false, false}, {256, 2, true, false},
                                    {256, 4, true, false}, {256, 4, true, true},
                                    {256, 2, true, true}};
 constexpr int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
-constexpr int kFusedZcFullRow = 64, kFusedZcTiled = 16;
+constexpr int kFusedZcTiled = 16, kFusedZcMin = 16;
 
 // LDS bytes of a prefetching tile: psi ring, own-plane and halo population buffers.
 constexpr int fused_pf_lds_bytes(int Q, int tx, int ty, bool fullx = true) {
@@ -63,21 +65,34 @@ constexpr int fused_pf64_lds_bytes(int Q, int tx, int ty) {
     return 4 * (ty + 2) * tx * 8 + 2 * Q * tx * ty * 4;
 }
 
-constexpr int default_fused_zc(const FusedCfg& c) { return c.fullx ? kFusedZcFullRow : kFusedZcTiled; }
-constexpr int default_fused_remap(const FusedCfg& c) { return (!c.fullx || c.pf) ? 1 : 0; }
+// Planes per z-chunk: for full-row tiles, nz split into round(cus / tiles) chunks (at least
+// one, at most nz / kFusedZcMin), e.g. 64 planes for 256x4 and 128 for 256x2 tiles at 256^3
+// on 256 CUs (measured at 256^3, ms per step, 128- vs 64-plane chunks with 256x2 tiles:
+// D3Q19 FP64 1.20 vs 1.24, D3Q27 FP32 0.756 vs 0.816, D3Q27 FP64 2.29 vs 2.34, D3Q27 FP16
+// 0.602 vs 0.638).
+constexpr int default_fused_zc(const FusedCfg& c, long long tiles, int nz, int cus) {
+    if (!c.fullx) return kFusedZcTiled;
+    long long n = (2 * (long long)cus + tiles) / (2 * tiles);
+    const long long nmax = nz / kFusedZcMin;
+    n = n < 1 ? 1 : n;
+    n = n > nmax ? (nmax < 1 ? 1 : nmax) : n;
+    return (int)((nz + n - 1) / n);
+}
+constexpr int default_fused_remap(const FusedCfg&) { return 1; }
 constexpr int default_fused_hints(const FusedCfg& c, int elem_bytes) {
     return (c.pf || elem_bytes != 8) ? kHintNtStore : 0;
 }
 
-// Default configuration for a 256-wide domain (measured at 256^3, ms per step):
+// Default configuration for a 256-wide domain (measured at 256^3, ms per step; the
+// comparisons made with 64-plane chunks are marked "64"):
 //   4-byte storage: prefetching 256x4 tiles where they fit in LDS (D3Q19: 0.506 vs 0.536
-//     plain), else prefetching 256x2 tiles (D3Q27: 0.800 vs 0.926 plain 256x2, 1.142 plain
-//     256x4, which spills);
-//   8-byte storage: plain 256x2 tiles for D3Q19 (1.25 vs 1.31 with the own-population
-//     prefetch of k_step_fused_pf64; 256x4 spills), prefetching 256x2 for D3Q27 (2.36 vs
-//     2.56 plain, 4.10 plain 256x4);
+//     plain), else prefetching 256x2 tiles (D3Q27: 0.76-0.78; 64: 0.800 vs 0.926 plain
+//     256x2, 1.142 plain 256x4, which spills);
+//   8-byte storage: plain 256x2 tiles for D3Q19 (1.19-1.22 vs 1.26-1.28 with the
+//     own-population prefetch of k_step_fused_pf64; 256x4 spills), prefetching 256x2 for
+//     D3Q27 (2.29-2.33; 64: 2.36 vs 2.56 plain, 4.10 plain 256x4);
 //   2-byte storage: prefetching 256x4 for D3Q19 (0.320 vs 0.342 plain), plain 256x2 for
-//     D3Q27 (0.630 vs 0.656 prefetching, 0.92 plain 256x4).
+//     D3Q27 (0.602-0.609 vs 0.645 prefetching; 64: 0.92 plain 256x4).
 constexpr int default_fused_cfg_index(int nx, int elem_bytes, int Q) {
     return nx != 256 ? 0
          : elem_bytes == 8 ? (Q == 27 && fused_pf64_lds_bytes(Q, 256, 2) <= kLdsBytesPerCU ? 4 : 1)
