@@ -504,6 +504,27 @@ static void fused_chunking(const lbm_ctx* c, int& zc, int& remap, int& hints) {
     zc = std::min(zc, c->p.nz);
 }
 
+// Calls f(geometry, store hint) with both as compile-time constants (std::integral_constant):
+// the step kernels are instantiated per geometry and per store hint.
+template <typename F>
+static void with_geom_nts(const lbm_ctx* c, int hints, F&& f) {
+    using std::integral_constant;
+    const bool nt = (hints & kHintNtStore) != 0;
+    switch (geom_of(c)) {
+    case GEOM_NONE:
+        if (nt) f(integral_constant<int, GEOM_NONE>{}, integral_constant<bool, true>{});
+        else f(integral_constant<int, GEOM_NONE>{}, integral_constant<bool, false>{});
+        break;
+    case GEOM_WALLS:
+        if (nt) f(integral_constant<int, GEOM_WALLS>{}, integral_constant<bool, true>{});
+        else f(integral_constant<int, GEOM_WALLS>{}, integral_constant<bool, false>{});
+        break;
+    default:
+        if (nt) f(integral_constant<int, GEOM_MASK>{}, integral_constant<bool, true>{});
+        else f(integral_constant<int, GEOM_MASK>{}, integral_constant<bool, false>{});
+    }
+}
+
 template <int Q, typename T, int TX, int TY, bool FULLX>
 static void launch_fused_cfg(lbm_ctx* c, const void* fin, void* fout) {
     using R = typename Arith<T>::type;
@@ -516,22 +537,12 @@ static void launch_fused_cfg(lbm_ctx* c, const void* fin, void* fout) {
     const int nchunks = (c->p.nz + zc - 1) / zc;
     const dim3 grid((unsigned)(tiles * nchunks)), block(TX * TY);
     // the kernel addresses populations with 32-bit byte offsets (checked at create)
-    switch (geom_of(c)) {
-    case GEOM_NONE:
-        hipLaunchKernelGGL((k_step_fused<Q, T, GEOM_NONE, TX, TY, FULLX>), grid, block, 0,
-                           c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), P, ntx, nty,
-                           zc, remap, hints);
-        break;
-    case GEOM_WALLS:
-        hipLaunchKernelGGL((k_step_fused<Q, T, GEOM_WALLS, TX, TY, FULLX>), grid, block, 0,
-                           c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), P, ntx, nty,
-                           zc, remap, hints);
-        break;
-    default:
-        hipLaunchKernelGGL((k_step_fused<Q, T, GEOM_MASK, TX, TY, FULLX>), grid, block, 0,
-                           c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), P, ntx, nty,
-                           zc, remap, hints);
-    }
+    with_geom_nts(c, hints, [&](auto geom, auto nts) {
+        hipLaunchKernelGGL((k_step_fused<Q, T, decltype(geom)::value, TX, TY, FULLX,
+                                         decltype(nts)::value>),
+                           grid, block, 0, c->stream, (const T*)fin, (T*)fout, c->solid,
+                           grid_of(c), P, ntx, nty, zc, remap, hints);
+    });
 }
 
 // Full-row tiles with the LDS prefetch: k_step_fused_pf for 2- and 4-byte storage,
@@ -547,41 +558,24 @@ static void launch_fused_pf(lbm_ctx* c, const void* fin, void* fout) {
         const dim3 grid((unsigned)(nty * nchunks)), block(TX * TY);
         const double* f0 = (const double*)fin;
         double* f1 = (double*)fout;
-        switch (geom_of(c)) {
-        case GEOM_NONE:
-            hipLaunchKernelGGL((k_step_fused_pf64<Q, GEOM_NONE, TX, TY>), grid, block, 0, c->stream,
-                               f0, f1, c->solid, grid_of(c), c->pd, zc, remap, hints);
-            break;
-        case GEOM_WALLS:
-            hipLaunchKernelGGL((k_step_fused_pf64<Q, GEOM_WALLS, TX, TY>), grid, block, 0, c->stream,
-                               f0, f1, c->solid, grid_of(c), c->pd, zc, remap, hints);
-            break;
-        default:
-            hipLaunchKernelGGL((k_step_fused_pf64<Q, GEOM_MASK, TX, TY>), grid, block, 0, c->stream,
-                               f0, f1, c->solid, grid_of(c), c->pd, zc, remap, hints);
-        }
+        with_geom_nts(c, hints, [&](auto geom, auto nts) {
+            hipLaunchKernelGGL((k_step_fused_pf64<Q, decltype(geom)::value, TX, TY,
+                                                  decltype(nts)::value>),
+                               grid, block, 0, c->stream, f0, f1, c->solid, grid_of(c), c->pd, zc,
+                               remap, hints);
+        });
     } else if constexpr ((sizeof(T) == 4 || sizeof(T) == 2) && fused_pf_lds_bytes(Q, TX, TY) <= kLdsBytesPerCU) {
         const int nty = (c->p.ny + TY - 1) / TY;
         int zc, remap, hints;
         fused_chunking(c, zc, remap, hints);
         const int nchunks = (c->p.nz + zc - 1) / zc;
         const dim3 grid((unsigned)(nty * nchunks)), block(TX * TY);
-        switch (geom_of(c)) {
-        case GEOM_NONE:
-            hipLaunchKernelGGL((k_step_fused_pf<Q, T, GEOM_NONE, TX, TY>), grid, block, 0,
-                               c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), c->pf, zc, remap,
-                               hints);
-            break;
-        case GEOM_WALLS:
-            hipLaunchKernelGGL((k_step_fused_pf<Q, T, GEOM_WALLS, TX, TY>), grid, block, 0,
-                               c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), c->pf, zc, remap,
-                               hints);
-            break;
-        default:
-            hipLaunchKernelGGL((k_step_fused_pf<Q, T, GEOM_MASK, TX, TY>), grid, block, 0,
-                               c->stream, (const T*)fin, (T*)fout, c->solid, grid_of(c), c->pf, zc, remap,
-                               hints);
-        }
+        with_geom_nts(c, hints, [&](auto geom, auto nts) {
+            hipLaunchKernelGGL((k_step_fused_pf<Q, T, decltype(geom)::value, TX, TY,
+                                                decltype(nts)::value>),
+                               grid, block, 0, c->stream, (const T*)fin, (T*)fout, c->solid,
+                               grid_of(c), c->pf, zc, remap, hints);
+        });
     } else {
         launch_fused_cfg<Q, T, TX, TY, true>(c, fin, fout);
     }
@@ -974,25 +968,30 @@ static lbm_status batch_fail(lbm_status s, const char* fmt, ...) {
                       #call, hipGetErrorString(e_)); } while (0)
 
 template <typename T, int TX, int TY>
-static void launch_batch(const lbm_batch* b, hipStream_t s, const void* table, bool pf) {
+static void launch_batch(const lbm_batch* b, hipStream_t s, const void* table, bool pf, bool nt) {
     const dim3 grid((unsigned)b->blocks), block(TX * TY);
     const DomainDesc<T>* tb = (const DomainDesc<T>*)table;
     const int nd = (int)b->ctx.size();
-    if constexpr (sizeof(T) == 4) {
-        if (pf) {
-            if (b->geom == GEOM_MASK)
-                hipLaunchKernelGGL((k_step_fused_batch_pf<19, T, GEOM_MASK, TX, TY>), grid, block,
-                                   0, s, tb, nd);
-            else
-                hipLaunchKernelGGL((k_step_fused_batch_pf<19, T, GEOM_WALLS, TX, TY>), grid, block,
-                                   0, s, tb, nd);
-            return;
+    auto go = [&](auto geom, auto nts) {
+        constexpr int G = decltype(geom)::value;
+        constexpr bool N = decltype(nts)::value;
+        if constexpr (sizeof(T) == 4) {
+            if (pf) {
+                hipLaunchKernelGGL((k_step_fused_batch_pf<19, T, G, TX, TY, N>), grid, block, 0, s,
+                                   tb, nd);
+                return;
+            }
         }
+        hipLaunchKernelGGL((k_step_fused_batch<19, T, G, TX, TY, N>), grid, block, 0, s, tb, nd);
+    };
+    using std::integral_constant;
+    if (b->geom == GEOM_MASK) {
+        if (nt) go(integral_constant<int, GEOM_MASK>{}, integral_constant<bool, true>{});
+        else go(integral_constant<int, GEOM_MASK>{}, integral_constant<bool, false>{});
+    } else {
+        if (nt) go(integral_constant<int, GEOM_WALLS>{}, integral_constant<bool, true>{});
+        else go(integral_constant<int, GEOM_WALLS>{}, integral_constant<bool, false>{});
     }
-    if (b->geom == GEOM_MASK)
-        hipLaunchKernelGGL((k_step_fused_batch<19, T, GEOM_MASK, TX, TY>), grid, block, 0, s, tb, nd);
-    else
-        hipLaunchKernelGGL((k_step_fused_batch<19, T, GEOM_WALLS, TX, TY>), grid, block, 0, s, tb, nd);
 }
 
 template <typename T>
@@ -1039,11 +1038,18 @@ static lbm_status build_tables(lbm_batch* b) {
     // Plain tiles: on serving mixes of box sizes (rows not 128-byte aligned) they beat the
     // prefetching tiles (19.2 vs 17.9 GLUPS) and 32x8 tiles (16.2); LBM_BATCH_PF=1 selects
     // the prefetching tiles for 4-byte storage (tuning).
-    bool pf = false;
+    // Nontemporal stores when every member's rows are whole 128-byte lines (serving shapes,
+    // GLUPS, nontemporal vs plain: 8x128^3 23.0 vs 22.6, 32x64^3 26.7 vs 26.2, 2x192^3 23.5
+    // vs 23.2; 24 mixed sizes, mostly unaligned rows: 18.1 vs 19.1).
+    bool pf = false, nt = true;
+    for (const lbm_ctx* c : b->ctx) nt = nt && ((long long)c->p.nx * (long long)c->elem) % 128 == 0;
     if (const char* e = getenv("LBM_BATCH_PF")) pf = sizeof(T) == 4 && atoi(e) != 0;
+    if (const char* e = getenv("LBM_BATCH_NT")) nt = atoi(e) != 0;              // tuning override
     for (int s = 0; s < b->steps_per_launch; ++s) {
-        if (b->tile == 0) launch_batch<T, kBatchTiles[0][0], kBatchTiles[0][1]>(b, cap, b->table[s & 1], pf);
-        else launch_batch<T, kBatchTiles[1][0], kBatchTiles[1][1]>(b, cap, b->table[s & 1], pf);
+        if (b->tile == 0)
+            launch_batch<T, kBatchTiles[0][0], kBatchTiles[0][1]>(b, cap, b->table[s & 1], pf, nt);
+        else
+            launch_batch<T, kBatchTiles[1][0], kBatchTiles[1][1]>(b, cap, b->table[s & 1], pf, nt);
     }
     ce = hipStreamEndCapture(cap, &b->graph);
     (void)hipStreamDestroy(cap);

@@ -36,6 +36,10 @@ namespace lbmk {
 //                     rows other tiles are about to pull);
 //   kHintNtInterior   prefetching tiles load the own pulls of their interior rows (read by
 //                     no other tile) with the nontemporal hint.
+// The store hint is a template parameter of the kernels (the host picks the instantiation):
+// a run-time branch between a plain and a nontemporal store of the same value to the same
+// address is merged by the compiler into one plain store, and two inlined copies of a tile
+// would double its LDS and spill.
 constexpr int kHintNtStore = 1, kHintNtInterior = 2;
 
 // Launch configurations of the fused step: tile width and height, whether the tile spans
@@ -79,8 +83,17 @@ constexpr int default_fused_zc(const FusedCfg& c, long long tiles, int nz, int c
     return (int)((nz + n - 1) / n);
 }
 constexpr int default_fused_remap(const FusedCfg&) { return 1; }
+// Cache hints (measured at 256^3, ms per step, plain stores vs nontemporal stores): full-row
+// prefetching 256x4 tiles, D3Q19 FP32 0.526 vs 0.486 (0.482 with nontemporal interior loads
+// too), FP16 0.323 vs 0.302; FP64 own-population prefetch 256x2, D3Q27 2.30 vs 2.11; plain
+// 256x2 tiles, D3Q27 FP16 0.607 vs 0.585. Plain stores elsewhere: prefetching 256x2 tiles,
+// D3Q27 FP32 0.761 vs 0.830; plain 256x2, D3Q19 FP64 1.19 vs 1.21; 32x8 tiles (300^2 x 250)
+// 1.30 vs 1.69 D3Q19 FP32, 1.86 vs 2.40 D3Q27 FP32, 2.08 vs 2.28 D3Q19 FP64 (a nontemporal
+// store of a partly written cache line costs more than a cached one).
 constexpr int default_fused_hints(const FusedCfg& c, int elem_bytes) {
-    return (c.pf || elem_bytes != 8) ? kHintNtStore : 0;
+    if (!c.fullx) return 0;
+    if (c.pf && elem_bytes == 4) return c.ty == 4 ? kHintNtStore | kHintNtInterior : 0;
+    return (elem_bytes == 2 || (c.pf && elem_bytes == 8)) ? kHintNtStore : 0;
 }
 
 // Default configuration for a 256-wide domain (measured at 256^3, ms per step; the
@@ -191,7 +204,7 @@ __device__ __forceinline__ R sum_q(const R* v) {
 // One tile (workgroup) of the fused step: tile index t of a domain with ntx x nty tiles
 // per plane and z-chunks of zc planes. Shared by the single-domain kernel and the
 // multi-domain (batched) kernel.
-template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX>
+template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX, bool NTS>
 __device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restrict__ fout,
                                            const uint8_t* __restrict__ solid, const Grid& g,
                                            const Phys<typename Arith<T>::type>& P,
@@ -296,7 +309,7 @@ __device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restr
             const NodeForce<R> nf = node_force<Q, R>(psi0, pn, P);
             collide<Q, R>(c, nf, P);
             const unsigned nb = (unsigned)(oxy[4] + z * nxy) * (unsigned)sizeof(T);
-            if (hints & kHintNtStore) {
+            if constexpr (NTS) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i) st_off_nt(fout, nb + (unsigned)i * pst, static_cast<T>(c[i]));
             } else {
@@ -327,6 +340,16 @@ __device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restr
 // Wait until every vector memory operation of this wavefront has completed (vmcnt(0); the
 // expcnt and lgkmcnt fields at their maxima, i.e. not waited for).
 __device__ __forceinline__ void wait_vector_memory() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// Wait until at most N vector memory operations of this wavefront are outstanding (vmcnt(N):
+// bits 3:0 and 15:14 of the immediate). Vector memory operations complete in issue order,
+// loads into VGPRs or LDS and stores alike (the compiler's own waits for a load followed by
+// a store count on this too), so when the last N issued were stores this waits for
+// everything issued before them and lets the stores drain.
+template <int N>
+__device__ __forceinline__ void wait_vector_memory_but() {
+    static_assert(N >= 0 && N < 64, "vmcnt is a 6-bit field");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
 // Workgroup barrier for LDS traffic only: every wavefront's LDS accesses complete, then
 // s_barrier. Unlike __syncthreads it does not wait for outstanding vector memory operations
 // (the asynchronous LDS loads in flight are read back only by the lanes that issued them,
@@ -379,7 +402,7 @@ __device__ __forceinline__ float pf_value<_Float16, float>(uint32_t v) {
     return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(v)));
 }
 
-template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX>
+template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX, bool NTS>
 __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __restrict__ fout,
                                               const uint8_t* __restrict__ solid, const Grid& g,
                                               const Phys<float>& P, int t, int ntx, int nty,
@@ -554,11 +577,16 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
     halo_psi(z0, 1);
     prefetch_halo(z0 + 1);
     prefetch_own(z0 + 1);
+    // true when this wavefront's last vector memory operations were the Q stores of the
+    // previous plane (some lane stored, so all Q store instructions were issued): the wait
+    // for the prefetched plane then leaves those stores in flight
+    bool stored = false;
     for (int z = z0; z < z1; ++z) {
         const int k = z - z0;
         const int s0 = k & 3, s1 = (k + 1) & 3, s2 = (k + 2) & 3;
         const bool more = z + 1 < z1;
-        wait_vector_memory();
+        if (stored) wait_vector_memory_but<Q>();
+        else wait_vector_memory();
         // each buffer is refilled with plane z+2 as soon as its plane z+1 has been read
         take_halo(z + 1, s2);
         wait_lds();
@@ -568,7 +596,9 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
         if (more) prefetch_own(z + 2);
         barrier_lds();
         const R psi0 = ring[s1][ly + 1][lx + OX];
-        if (active && !(psi0 < R(0))) {
+        const bool fluid_node = active && !(psi0 < R(0));
+        stored = __any(fluid_node);
+        if (fluid_node) {
             R pn[Q];
 #pragma unroll
             for (int j = 0; j < Q; ++j) {
@@ -579,7 +609,7 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
             const NodeForce<R> nf = node_force<Q, R>(psi0, pn, P);
             collide<Q, R>(cur, nf, P);
             const unsigned nb = (unsigned)(oxy[4] + z * nxy) * (unsigned)sizeof(T);
-            if (hints & kHintNtStore) {
+            if constexpr (NTS) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i)
                     st_off_nt(fout, nb + (unsigned)i * pst, static_cast<T>(cur[i]));
@@ -599,7 +629,7 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
 // for the halo loads after the prefetch would also wait for the prefetch. The own buffer
 // (77.8 KB at 256x2, D3Q19) and the psi ring (32 KB) fit in LDS; a halo buffer would not.
 // Arithmetic per node as in fused_tile (bitwise identical results).
-template <int Q, int GEOM, int TX, int TY>
+template <int Q, int GEOM, int TX, int TY, bool NTS>
 __device__ __forceinline__ void fused_tile_pf64(const double* __restrict__ fin,
                                                 double* __restrict__ fout,
                                                 const uint8_t* __restrict__ solid, const Grid& g,
@@ -728,7 +758,7 @@ __device__ __forceinline__ void fused_tile_pf64(const double* __restrict__ fin,
             const NodeForce<R> nf = node_force<Q, R>(psi0, pn, P);
             collide<Q, R>(cur, nf, P);
             const unsigned nb = (unsigned)(oxy[4] + z * nxy) * (unsigned)sizeof(T);
-            if (hints & kHintNtStore) {
+            if constexpr (NTS) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i) st_off_nt(fout, nb + (unsigned)i * pst, cur[i]);
             } else {
@@ -741,30 +771,30 @@ __device__ __forceinline__ void fused_tile_pf64(const double* __restrict__ fin,
     }
 }
 
-template <int Q, int GEOM, int TX, int TY>
+template <int Q, int GEOM, int TX, int TY, bool NTS>
 __global__ __launch_bounds__(TX * TY) void k_step_fused_pf64(const double* __restrict__ fin,
                                                             double* __restrict__ fout,
                                                             const uint8_t* __restrict__ solid,
                                                             Grid g, Phys<double> P, int zc,
                                                             int remap, int hints) {
     const int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    fused_tile_pf64<Q, GEOM, TX, TY>(fin, fout, solid, g, P, t, (g.ny + TY - 1) / TY, zc, hints);
+    fused_tile_pf64<Q, GEOM, TX, TY, NTS>(fin, fout, solid, g, P, t, (g.ny + TY - 1) / TY, zc, hints);
 }
 
-template <int Q, typename T, int GEOM, int TX, int TY>
+template <int Q, typename T, int GEOM, int TX, int TY, bool NTS>
 __global__ __launch_bounds__(TX * TY) void k_step_fused_pf(const T* __restrict__ fin,
                                                           T* __restrict__ fout,
                                                           const uint8_t* __restrict__ solid,
                                                           Grid g, Phys<float> P, int zc,
                                                           int remap, int hints) {
     const int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    fused_tile_pf<Q, T, GEOM, TX, TY, true>(fin, fout, solid, g, P, t, 1,
-                                            (g.ny + TY - 1) / TY, zc, hints);
+    fused_tile_pf<Q, T, GEOM, TX, TY, true, NTS>(fin, fout, solid, g, P, t, 1,
+                                                 (g.ny + TY - 1) / TY, zc, hints);
 }
 
 // Single domain. remap != 0: map workgroups to tiles so that each XCD gets a contiguous
 // tile range (workgroup b runs on XCD b mod 8).
-template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX>
+template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX, bool NTS>
 __global__ __launch_bounds__(TX * TY) void k_step_fused(const T* __restrict__ fin,
                                                        T* __restrict__ fout,
                                                        const uint8_t* __restrict__ solid,
@@ -772,7 +802,7 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(const T* __restrict__ fi
                                                        int ntx, int nty, int zc, int remap,
                                                        int hints) {
     const int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    fused_tile<Q, T, GEOM, TX, TY, FULLX>(fin, fout, solid, g, P, t, ntx, nty, zc, hints);
+    fused_tile<Q, T, GEOM, TX, TY, FULLX, NTS>(fin, fout, solid, g, P, t, ntx, nty, zc, hints);
 }
 
 // One domain of a batched step: its buffers, geometry, physics and the first workgroup
@@ -789,7 +819,7 @@ struct DomainDesc {
 
 // Many independent lattices advanced by one launch: workgroup b belongs to the last
 // domain whose block0 <= b (binary search over the table, uniform per workgroup).
-template <int Q, typename T, int GEOM, int TX, int TY>
+template <int Q, typename T, int GEOM, int TX, int TY, bool NTS>
 __global__ __launch_bounds__(TX * TY) void k_step_fused_batch(const DomainDesc<T>* __restrict__ d,
                                                              int ndom) {
     const int b = blockIdx.x;
@@ -799,12 +829,12 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_batch(const DomainDesc<T
         if (d[mid].block0 <= b) lo = mid; else hi = mid - 1;
     }
     const DomainDesc<T>& D = d[lo];
-    fused_tile<Q, T, GEOM, TX, TY, false>(D.fin, D.fout, D.solid, D.g, D.P, b - D.block0,
-                                                D.ntx, D.nty, D.zc, kHintNtStore);
+    fused_tile<Q, T, GEOM, TX, TY, false, NTS>(D.fin, D.fout, D.solid, D.g, D.P, b - D.block0,
+                                               D.ntx, D.nty, D.zc, 0);
 }
 
 // Batched step with prefetching tiles (4-byte storage): as k_step_fused_batch.
-template <int Q, typename T, int GEOM, int TX, int TY>
+template <int Q, typename T, int GEOM, int TX, int TY, bool NTS>
 __global__ __launch_bounds__(TX * TY) void k_step_fused_batch_pf(const DomainDesc<T>* __restrict__ d,
                                                                 int ndom) {
     const int b = blockIdx.x;
@@ -814,8 +844,8 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_batch_pf(const DomainDes
         if (d[mid].block0 <= b) lo = mid; else hi = mid - 1;
     }
     const DomainDesc<T>& D = d[lo];
-    fused_tile_pf<Q, T, GEOM, TX, TY, false>(D.fin, D.fout, D.solid, D.g, D.P, b - D.block0,
-                                             D.ntx, D.nty, D.zc, kHintNtStore);
+    fused_tile_pf<Q, T, GEOM, TX, TY, false, NTS>(D.fin, D.fout, D.solid, D.g, D.P, b - D.block0,
+                                                  D.ntx, D.nty, D.zc, 0);
 }
 
 }  // namespace lbmk

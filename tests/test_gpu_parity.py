@@ -266,7 +266,8 @@ def test_fused_prefetch_tiles_bitwise_equal_plain_tiles(L, monkeypatch, geom, Q,
     32x8 tiles (0): the per-node arithmetic is the same, so the populations agree bit for
     bit. Ragged y extent (10 rows of 4-row tiles) and several z-chunks (LBM_FUSED_ZC = 7
     over nz = 20). D3Q27 does not fit the 256x4 prefetch buffers and runs plain 256x4 tiles
-    under configuration 3."""
+    under configuration 3. Each configuration also runs with the other store hint
+    (LBM_FUSED_HINTS: nontemporal or plain stores, separate kernel instantiations)."""
     walls = {"periodic": (), "walls": ("z_lo", "z_hi", "y_lo"), "cylinder": ("z_lo",)}[geom]
     cyl = (5.0, 9.0, 3.0) if geom == "cylinder" else None
     w = si.Workload("pf", Q, 256, 10, 20, T_over_Tc=0.7, walls=walls, cylinder=cyl, G_ads=0.05,
@@ -275,15 +276,21 @@ def test_fused_prefetch_tiles_bitwise_equal_plain_tiles(L, monkeypatch, geom, Q,
     rv, rl = maxwell(w)
     out = {}
     monkeypatch.setenv("LBM_FUSED_ZC", "7")
-    for cfg in ("3", "4", "2", "1", "0"):
+    runs = [(c, None) for c in ("3", "4", "2", "1", "0")] + [(c, h) for c in ("3", "4", "1", "0")
+                                                              for h in ("0", "1")]
+    for cfg, hints in runs:
         monkeypatch.setenv("LBM_FUSED_CONFIG", cfg)
+        if hints is None:
+            monkeypatch.delenv("LBM_FUSED_HINTS", raising=False)
+        else:
+            monkeypatch.setenv("LBM_FUSED_HINTS", hints)
         ref = 0.0 if storage == "fp64" else rv
         with L.Lattice(gpu_params(w, storage, rho_ref=ref)) as lat:
             lat.init_droplet(*w.droplet_centre(), w.R, w.W, rl, rv, *w.U, w.noise, w.seed)
             lat.step(12)
-            out[cfg] = lat.get_populations()
-    for cfg in ("4", "2", "1", "0"):
-        assert np.array_equal(out["3"], out[cfg]), cfg
+            out[(cfg, hints)] = lat.get_populations()
+    for key in runs[1:]:
+        assert np.array_equal(out[("3", None)], out[key]), key
 
 
 def _sampled_window_errors(w, f3, f4, centres, solid=None, h=6):
