@@ -484,7 +484,8 @@ static const char* const kFusedNames[] = {"k_step_fused"};
 static int default_fused_cfg(const lbm_ctx* c) {
     if (const char* e = getenv("LBM_FUSED_CONFIG")) {      // tuning override
         const int v = atoi(e);
-        if (v >= 0 && v < kNumFusedCfgs && (!kFusedCfgs[v].fullx || c->p.nx == kFusedCfgs[v].tx))
+        if (v >= 0 && v < kNumFusedCfgs && (!kFusedCfgs[v].fullx || c->p.nx == kFusedCfgs[v].tx) &&
+            !(c->elem == 8 && kFusedCfgs[v].tx > 256))
             return v;
     }
     return default_fused_cfg_index(c->p.nx, (int)c->elem, c->Q);
@@ -581,6 +582,21 @@ static void launch_fused_pf(lbm_ctx* c, const void* fin, void* fout) {
     }
 }
 
+// 320- and 384-wide full rows (2-row tiles) for 2- and 4-byte storage only: FP64 needs more
+// VGPRs than 640 or 768 threads leave a lane (12.3 vs 9.4 GLUPS, 32x8 vs 384x2 at 384^2 x 160),
+// so FP64 is not instantiated here and never selected (default_fused_cfg).
+template <int Q, typename T>
+static void launch_fused_wide(lbm_ctx* c, const void* fin, void* fout) {
+    if constexpr (sizeof(T) != 8) {
+        switch (c->fused_cfg) {
+        case 5: launch_fused_cfg<Q, T, 320, 2, true>(c, fin, fout); break;
+        case 6: launch_fused_pf<Q, T, 320, 2>(c, fin, fout); break;
+        case 7: launch_fused_cfg<Q, T, 384, 2, true>(c, fin, fout); break;
+        default: launch_fused_pf<Q, T, 384, 2>(c, fin, fout); break;
+        }
+    }
+}
+
 template <int Q, typename T>
 static void launch_fused(lbm_ctx* c, const void* fin, void* fout) {
     switch (c->fused_cfg) {
@@ -588,6 +604,7 @@ static void launch_fused(lbm_ctx* c, const void* fin, void* fout) {
     case 2: launch_fused_cfg<Q, T, 256, 4, true>(c, fin, fout); break;
     case 3: launch_fused_pf<Q, T, 256, 4>(c, fin, fout); break;
     case 4: launch_fused_pf<Q, T, 256, 2>(c, fin, fout); break;
+    case 5: case 6: case 7: case 8: launch_fused_wide<Q, T>(c, fin, fout); break;
     default: launch_fused_cfg<Q, T, 32, 8, false>(c, fin, fout); break;
     }
 }

@@ -45,15 +45,17 @@ constexpr int kHintNtStore = 1, kHintNtInterior = 2;
 // Launch configurations of the fused step: tile width and height, whether the tile spans
 // the whole x row (then nx must equal tx), and pf: the next planes are prefetched into LDS
 // (k_step_fused_pf; 2- or 4-byte storage, and the populations of a tile plus its halo rows
-// must fit in LDS). 32x8 tiles serve widths other than 256. Full-row tiles cut z into as many
-// chunks as it takes for about one workgroup per CU (each holds a CU alone: LDS or VGPRs), so
-// every workgroup marches as far as possible and the two lead-in planes of a chunk are paid
-// rarely; small tiles march through 16-plane chunks. Both map tiles to XCDs in contiguous
-// ranges.
+// must fit in LDS). Full rows of 256, 320 and 384 nodes; 32x8 tiles serve other widths.
+// Full-row tiles cut z into chunks sized for whole rounds of one workgroup per CU (each holds
+// a CU alone: LDS or VGPRs), so every workgroup marches as far as possible and the two
+// lead-in planes of a chunk are paid rarely; small tiles march through 16-plane chunks. Both
+// map tiles to XCDs in contiguous ranges.
 struct FusedCfg { int tx, ty; bool fullx, pf; };
 constexpr FusedCfg kFusedCfgs[] = {{32, 8, false, false}, {256, 2, true, false},
                                    {256, 4, true, false}, {256, 4, true, true},
-                                   {256, 2, true, true}};
+                                   {256, 2, true, true},  {320, 2, true, false},
+                                   {320, 2, true, true},  {384, 2, true, false},
+                                   {384, 2, true, true}};
 constexpr int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
 constexpr int kFusedZcTiled = 16, kFusedZcMin = 16;
 
@@ -69,18 +71,25 @@ constexpr int fused_pf64_lds_bytes(int Q, int tx, int ty) {
     return 4 * (ty + 2) * tx * 8 + 2 * Q * tx * ty * 4;
 }
 
-// Planes per z-chunk: for full-row tiles, nz split into round(cus / tiles) chunks (at least
-// one, at most nz / kFusedZcMin), e.g. 64 planes for 256x4 and 128 for 256x2 tiles at 256^3
-// on 256 CUs (measured at 256^3, ms per step, 128- vs 64-plane chunks with 256x2 tiles:
-// D3Q19 FP64 1.20 vs 1.24, D3Q27 FP32 0.756 vs 0.816, D3Q27 FP64 2.29 vs 2.34, D3Q27 FP16
-// 0.602 vs 0.638).
+// Planes per z-chunk for full-row tiles: nz is cut into n chunks, n minimising
+// rounds(n) x (planes per chunk + 2 lead-in planes), where a round is one workgroup on each
+// of the cus CUs; e.g. 64 planes for 256x4 and 128 for 256x2 tiles at 256^3 (one round),
+// 48 for 384x2 tiles at 384^2 x 192 (three rounds of 256 over 192 tiles x 4 chunks).
+// Measured at 256^3, ms per step, 128- vs 64-plane chunks with 256x2 tiles: D3Q19 FP64 1.20
+// vs 1.24, D3Q27 FP32 0.756 vs 0.816, D3Q27 FP64 2.29 vs 2.34, D3Q27 FP16 0.602 vs 0.638.
 constexpr int default_fused_zc(const FusedCfg& c, long long tiles, int nz, int cus) {
     if (!c.fullx) return kFusedZcTiled;
-    long long n = (2 * (long long)cus + tiles) / (2 * tiles);
-    const long long nmax = nz / kFusedZcMin;
-    n = n < 1 ? 1 : n;
-    n = n > nmax ? (nmax < 1 ? 1 : nmax) : n;
-    return (int)((nz + n - 1) / n);
+    const int nmax = nz / kFusedZcMin < 1 ? 1 : (nz / kFusedZcMin > 64 ? 64 : nz / kFusedZcMin);
+    int best_zc = nz;
+    long long best = -1;
+    for (int n = 1; n <= nmax; ++n) {
+        const int zc = (nz + n - 1) / n;
+        const long long chunks = (nz + zc - 1) / zc;
+        const long long rounds = (tiles * chunks + cus - 1) / cus;
+        const long long cost = rounds * (zc + 2);
+        if (best < 0 || cost < best) { best = cost; best_zc = zc; }
+    }
+    return best_zc;
 }
 constexpr int default_fused_remap(const FusedCfg&) { return 1; }
 // Cache hints (measured at 256^3, ms per step, plain stores vs nontemporal stores): full-row
@@ -106,8 +115,17 @@ constexpr int default_fused_hints(const FusedCfg& c, int elem_bytes) {
 //     D3Q27 (2.29-2.33; 64: 2.36 vs 2.56 plain, 4.10 plain 256x4);
 //   2-byte storage: prefetching 256x4 for D3Q19 (0.320 vs 0.342 plain), plain 256x2 for
 //     D3Q27 (0.602-0.609 vs 0.645 prefetching; 64: 0.92 plain 256x4).
+// 320- and 384-wide domains (GLUPS; 2-row full-row tiles vs 32x8 tiles): D3Q19 prefetching
+// (FP32 384^2 x 192 30.0 vs 22.0, 27.3 plain; 320 x 256 x 192 28.6 vs 22.2; FP16 384^2 x 192
+// 43-45 vs 30.7), D3Q27 plain (320 x 256 x 192 FP32 19.3 vs 15.5, 19.3 prefetching, which
+// spills; FP16 28.1 vs 21.5); FP64 stays on 32x8 tiles (12.3-12.7 vs 9.4 at 384^2 x 160,
+// 6.7-7.1 vs 5.4-5.6 for D3Q27 at 320 x 256 x 192: 640 or 768 threads leave too few VGPRs).
 constexpr int default_fused_cfg_index(int nx, int elem_bytes, int Q) {
-    return nx != 256 ? 0
+    return (nx == 320 || nx == 384)
+               ? (elem_bytes == 8 ? 0
+                  : Q == 19 && fused_pf_lds_bytes(Q, nx, 2) <= kLdsBytesPerCU ? (nx == 320 ? 6 : 8)
+                  : (nx == 320 ? 5 : 7))
+         : nx != 256 ? 0
          : elem_bytes == 8 ? (Q == 27 && fused_pf64_lds_bytes(Q, 256, 2) <= kLdsBytesPerCU ? 4 : 1)
          : elem_bytes == 4 ? (fused_pf_lds_bytes(Q, 256, 4) <= kLdsBytesPerCU ? 3
                               : fused_pf_lds_bytes(Q, 256, 2) <= kLdsBytesPerCU ? 4 : 1)

@@ -170,7 +170,9 @@ def serve(trace, mode="batched", storage="fp32", budget_bytes=64 << 30, max_slot
         ext = torch.cuda.ExternalStream(stream)
     while pending or active or retiring or futures:
         t = now()
-        # admission: arrived requests, while slots and the footprint budget allow
+        # admission: arrived requests, while slots and the footprint budget allow; lattices
+        # whose results are still being read back (futures) still hold their memory
+        over_budget = False
         while pending and pending[0]["t_arrival"] <= t:
             if mode == "sequential" and (active or retiring):
                 break
@@ -178,7 +180,8 @@ def serve(trace, mode="batched", storage="fp32", budget_bytes=64 << 30, max_slot
                 break
             p, _, _ = request_params(pending[0], storage)
             fp = L.lbm_footprint_bytes(p)
-            if (active or retiring) and used + fp > budget_bytes:
+            if (active or retiring or futures) and used + fp > budget_bytes:
+                over_budget = True
                 break
             if active and sum(int(j.req["L"]) ** 3 for j in active) >= max_active_nodes:
                 break
@@ -233,7 +236,7 @@ def serve(trace, mode="batched", storage="fp32", budget_bytes=64 << 30, max_slot
         retiring = finished
         collect(block=False)
         if not active and not retiring:
-            if futures and (not pending or pending[0]["t_arrival"] > now()):
+            if futures and (over_budget or not pending or pending[0]["t_arrival"] > now()):
                 collect(block=True)
             elif pending:
                 wait = (pending[0]["t_arrival"] - now()) / time_scale

@@ -293,6 +293,60 @@ def test_fused_prefetch_tiles_bitwise_equal_plain_tiles(L, monkeypatch, geom, Q,
         assert np.array_equal(out[("3", None)], out[key]), key
 
 
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+@pytest.mark.parametrize("geom", ["periodic", "walls", "cylinder"])
+@pytest.mark.parametrize("Q", [19, 27])
+@pytest.mark.parametrize("nx", [320, 384])
+def test_fused_wide_full_row_tiles_bitwise_equal_small_tiles(L, monkeypatch, nx, Q, geom, storage):
+    """320- and 384-wide domains: plain (5, 7) and prefetching (6, 8) 2-row full-row tiles,
+    with either store hint, against the 32x8 tiles (0): bit-equal populations after 12 steps.
+    Ragged y extent (9 rows of 2-row tiles) and several z-chunks (LBM_FUSED_ZC = 7 over
+    nz = 20). D3Q27 at 384 does not fit the prefetch buffers and runs plain tiles under 8."""
+    walls = {"periodic": (), "walls": ("z_lo", "z_hi", "y_lo"), "cylinder": ("z_lo",)}[geom]
+    cyl = (4.5, 9.0, 3.0) if geom == "cylinder" else None
+    w = si.Workload("wide", Q, nx, 9, 20, T_over_Tc=0.7, walls=walls, cylinder=cyl, G_ads=0.05,
+                    R=7.0, centre=(nx // 2, 4, 10), U=(0.01, 0.0, -0.02), noise=0.01, seed=11,
+                    nu=0.08, kappa=0.2)
+    rv, rl = maxwell(w)
+    plain, pf = ("5", "6") if nx == 320 else ("7", "8")
+    runs = [("0", None), (plain, "0"), (plain, "1"), (pf, "0"), (pf, "1")]
+    out = {}
+    monkeypatch.setenv("LBM_FUSED_ZC", "7")
+    for cfg, hints in runs:
+        monkeypatch.setenv("LBM_FUSED_CONFIG", cfg)
+        if hints is None:
+            monkeypatch.delenv("LBM_FUSED_HINTS", raising=False)
+        else:
+            monkeypatch.setenv("LBM_FUSED_HINTS", hints)
+        with L.Lattice(gpu_params(w, storage, rho_ref=rv)) as lat:
+            lat.init_droplet(*w.droplet_centre(), w.R, w.W, rl, rv, *w.U, w.noise, w.seed)
+            lat.step(12)
+            out[(cfg, hints)] = lat.get_populations()
+    for key in runs[1:]:
+        assert np.array_equal(out[runs[0]], out[key]), key
+
+
+def test_wide_default_configuration_matches_oracle(L):
+    """The 384-wide default (prefetching 384x2 full-row tiles, FP32 shifted storage, walls)
+    against the FP64 oracle over 5 steps on a thin box."""
+    w = si.Workload("wide", 19, 384, 6, 12, T_over_Tc=0.7, walls=("z_lo", "z_hi"), G_ads=0.05,
+                    R=5.0, centre=(190, 3, 6), U=(0.01, 0.0, -0.02), noise=0.01, seed=12,
+                    nu=0.08, kappa=0.2)
+    rv, rl = maxwell(w)
+    P = oracle_params(w)
+    with L.Lattice(gpu_params(w, "fp32", rho_ref=rv)) as lat:
+        lat.init_droplet(*w.droplet_centre(), w.R, w.W, rl, rv, *w.U, w.noise, w.seed)
+        f0 = lat.get_populations()
+        lat.step(5)
+        g = lat.get_populations()
+    f = olbm.run(f0, P, 5)
+    fluid = ~olbm.solid_mask(P)
+    rho_o, rho_g = f.sum(0)[fluid], g.sum(0)[fluid]
+    err = float(np.max(np.abs(rho_g - rho_o) / rho_o))
+    print(f"384x6x12 FP32 default tiles, 5 steps: max relative rho error {err:.2e}")
+    assert err < 1e-5, err
+
+
 def _sampled_window_errors(w, f3, f4, centres, solid=None, h=6):
     """Advance 13^3 windows of the read-back state f3 one step with the oracle (the solid
     mask, if any, cut from the full domain) and return the worst pointwise relative rho
@@ -317,9 +371,9 @@ def _sampled_window_errors(w, f3, f4, centres, solid=None, h=6):
 def test_full_size_impact_384x384x192_sampled_windows(L):
     """The droplet-impact workload at full size (384 x 384 x 192 D3Q19, walls z = 0 and
     z = 191, CS at 0.55 T_c, R = 40 at z = 50 falling at 0.05, nu = 0.001, FP32 shifted
-    storage) in its default launch configuration (32x8 tiles): one GPU step from a
-    read-back state against the oracle on windows at both walls, the droplet's foot,
-    interface and interior, the vapour and random places. G_ads = 0 (the config's 90 degree
+    storage) in its default launch configuration (prefetching 384x2 full-row tiles, 48-plane
+    z-chunks): one GPU step from a read-back state against the oracle on windows at both
+    walls, the droplet's foot, interface and interior, the vapour and random places. G_ads = 0 (the config's 90 degree
     wall is nominal: the wetting force enters through the same code path at any value)."""
     w = si.IMPACT_384
     rv, rl = maxwell(w)
@@ -346,8 +400,10 @@ def test_full_size_cylinder_d3q27_sampled_windows(L, storage):
     """The D3Q27 cylinder-impact workload at full size (320 x 256 x 192, walls z = 0 and
     z = 191, cylinder of radius 20 along x resting on the wall, CS at 0.6 T_c, R = 30
     falling at 0.04, wetting G_ads = 0.2): one GPU step against the oracle on windows on the
-    cylinder surface, the wall, the droplet and random places. FP64 to 1e-12 relative in
-    rho; FP32 shifted storage to 1e-6; FP16 shifted storage reported (bound 5e-3)."""
+    cylinder surface, the wall, the droplet and random places, each storage in its default
+    launch configuration (FP32 and FP16: plain 320x2 full-row tiles; FP64: 32x8 tiles).
+    FP64 to 1e-12 relative in rho; FP32 shifted storage to 1e-6; FP16 shifted storage
+    reported (bound 5e-3)."""
     w = si.CYLINDER_D3Q27
     rv, rl = maxwell(w)
     ref = 0.0 if storage == "fp64" else rv

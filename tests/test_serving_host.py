@@ -20,6 +20,7 @@ class Recorder:
         self.peak_bytes = 0
         self.peak_alive = 0
         self.log = []              # ctx of every step call, in order
+        self.peak_batch = 0        # most lattices in one batched launch
 
 
 def install_fakes(monkeypatch, rec):
@@ -65,6 +66,8 @@ def install_fakes(monkeypatch, rec):
             self.ctxs, self.spl = list(ctxs), spl
 
     def batch_create(ctxs, spl, stream=None):
+        with rec.lock:
+            rec.peak_batch = max(rec.peak_batch, len(ctxs))
         return FakeBatch(ctxs, spl)
 
     def batch_run(b, n):
@@ -120,8 +123,10 @@ def test_batched_loop_completes_every_request_within_budget(monkeypatch, budget_
     # every lattice took exactly its request's (rounded) step count and was freed
     assert not rec.alive
     assert sorted(rec.closed.values()) == sorted(serving.steps_of(r) for r in trace)
+    # lattices whose results are still being read back hold their memory until freed:
+    # the budget covers them; the slot limit bounds the lattices of one batched launch
     assert rec.peak_bytes <= budget
-    assert rec.peak_alive <= max_slots + 2       # retiring lattices are freed one chunk later
+    assert rec.peak_batch <= max_slots
     assert all(r["latency"] >= 0 for r in out["records"])
 
 
