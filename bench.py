@@ -162,6 +162,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--fp64-steps", type=int, default=100)
     ap.add_argument("--fp16-steps", type=int, default=100)
+    ap.add_argument("--slab-steps", type=int, default=200,
+                    help="steps on one GPU's z-slab of the workload shared by 8 GPUs (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rho-ref", default="vapour", choices=["zero", "vapour", "liquid"])
     ap.add_argument("--step-kernel", default="fused", choices=["fused", "two_pass"])
@@ -185,6 +187,16 @@ def main():
     r32 = run_gpu(w, "fp32", args.steps, args.warmup, args.rho_ref, args.step_kernel)
     r64 = run_gpu(w, "fp64", args.fp64_steps, max(2, args.warmup // 4), "zero", args.step_kernel)
     r16 = run_gpu(w, "fp16", args.fp16_steps, max(2, args.warmup // 4), args.rho_ref, args.step_kernel)
+    # one GPU's share if the 256^3 lattice were cut into 8 z-slabs (periodic slab: the halo
+    # exchange between GPUs is not part of this build)
+    slab = None
+    if args.slab_steps > 0:
+        ws = w.with_(nz=w.nz // 8, R=w.nz // 16 - 4.0, centre=(w.nx / 2, w.ny / 2, w.nz // 16))
+        rs = run_gpu(ws, "fp32", args.slab_steps, args.warmup, args.rho_ref, args.step_kernel)
+        slab = {"shape": [ws.nx, ws.ny, ws.nz], "value": round(rs["mlups"], 1), "unit": "MLUPS",
+                "us_per_step": round(1000 * rs["ms_per_step"], 1),
+                "kernel_us": round(1000 * max(rs["kernel_ms"].values()), 1),
+                "steps": args.slab_steps, "storage": "fp32 shifted"}
     copy_gbs = copy_bandwidth()
     stream_copy_gbs = L.lbm_copy_bandwidth()
 
@@ -230,6 +242,7 @@ def main():
                  "storage": "fp16 shifted", "effective_GBs": round(eff16, 1),
                  "effective_frac": round(eff16 / HBM_PEAK_GBS, 4),
                  "kernel_ms": r16["kernel_ms"]},
+        "slab_of_8": slab,
         "effective_step_GBs": round(effective, 1),
         "effective_step_frac": round(effective / HBM_PEAK_GBS, 4),
         "kernel_ms": r32["kernel_ms"],

@@ -57,7 +57,7 @@ constexpr FusedCfg kFusedCfgs[] = {{32, 8, false, false}, {256, 2, true, false},
                                    {320, 2, true, true},  {384, 2, true, false},
                                    {384, 2, true, true}};
 constexpr int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
-constexpr int kFusedZcTiled = 16, kFusedZcMin = 16;
+constexpr int kFusedZcTiled = 16, kFusedZcMin = 8;
 
 // LDS bytes of a prefetching tile: psi ring, own-plane and halo population buffers.
 constexpr int fused_pf_lds_bytes(int Q, int tx, int ty, bool fullx = true) {
@@ -74,7 +74,9 @@ constexpr int fused_pf64_lds_bytes(int Q, int tx, int ty) {
 // Planes per z-chunk for full-row tiles: nz is cut into n chunks, n minimising
 // rounds(n) x (planes per chunk + 2 lead-in planes), where a round is one workgroup on each
 // of the cus CUs; e.g. 64 planes for 256x4 and 128 for 256x2 tiles at 256^3 (one round),
-// 48 for 384x2 tiles at 384^2 x 192 (three rounds of 256 over 192 tiles x 4 chunks).
+// 48 for 384x2 tiles at 384^2 x 192 (three rounds of 256 over 192 tiles x 4 chunks), 8 for
+// a 256 x 256 x 32 slab (one GPU's share of 256^3 on eight: 70 us per step with 8-plane
+// chunks, 100 us with 16, 173 us with 32).
 // Measured at 256^3, ms per step, 128- vs 64-plane chunks with 256x2 tiles: D3Q19 FP64 1.20
 // vs 1.24, D3Q27 FP32 0.756 vs 0.816, D3Q27 FP64 2.29 vs 2.34, D3Q27 FP16 0.602 vs 0.638.
 constexpr int default_fused_zc(const FusedCfg& c, long long tiles, int nz, int cus) {
