@@ -133,7 +133,12 @@ lbm_status lbm_get_populations(lbm_ctx* c, double* f);
    F_int of Eq. (16), F_ads of Eq. (22), Q_ab of Eq. (B2), the moment-space collision of
    Eq. (8) with the forcing moments of Eq. (B1), f_bar* = M^-1 m*). Enqueues on the
    context stream and returns without waiting, except every reduce_every steps, where the
-   result of the previous health check is read. nsteps >= 0.                          */
+   result of the previous health check is read. nsteps >= 0.
+   The launch configuration of the fused step (tile shape: full rows for nx = 256, 320 or
+   384, else 32x8 tiles; z-chunk length; nontemporal hints) is chosen from the domain width,
+   the storage type and the lattice. For tuning, the environment variables
+   LBM_FUSED_CONFIG, LBM_FUSED_ZC, LBM_FUSED_REMAP and LBM_FUSED_HINTS override it; every
+   configuration gives bitwise the same populations.                                   */
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps);
 
 /* Number of time steps taken since the last initialisation.                           */
@@ -191,7 +196,10 @@ int64_t lbm_footprint_bytes(const lbm_params* p);
  * contexts (D3Q19, all FP32 or all FP64 storage, each initialised) and advances all of
  * them together: one kernel launch per time step covers the tiles of every member, and
  * steps_per_launch consecutive launches are captured once into a HIP graph. Each member
- * takes exactly the time step of lbm_step (same results up to rounding order).
+ * takes exactly the time step of lbm_step (bitwise the same populations: the per-node
+ * arithmetic is shared). The batched step runs 64x4 tiles through 16-plane z-chunks, with
+ * nontemporal stores when every member's rows are whole 128-byte lines; LBM_BATCH_TILE,
+ * LBM_BATCH_ZC, LBM_BATCH_PF and LBM_BATCH_NT override this for tuning.
  * The batch borrows the contexts (they must outlive it and must not be stepped on their
  * own while the batch runs); it orders its work after, and each member's later work
  * after, the batch's graph launches through events.
