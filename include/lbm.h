@@ -106,7 +106,8 @@ lbm_status lbm_create(const lbm_params* p, lbm_ctx** out);
 /* Free everything the context owns. NULL is accepted.                                 */
 lbm_status lbm_destroy(lbm_ctx* c);
 
-/* Message of the last failed call on c (or of the last failed lbm_create if c == NULL).*/
+/* Message of the last failed call on c (or, if c == NULL, of the last failed lbm_create
+   of the calling thread).                                                              */
 const char* lbm_last_error(const lbm_ctx* c);
 
 /* Initial state f_bar = M^-1 m^eq(rho0, u0) (Sec. II B) of a droplet centred at
@@ -208,7 +209,11 @@ typedef struct lbm_batch lbm_batch;
 
 /* Build a batch of n distinct contexts. steps_per_launch: even, >= 2 (time steps per
    graph replay). stream: hipStream_t for the replays, or NULL for a batch-owned stream.
-   Does not wait for the members' pending work (lbm_batch_run orders after it).         */
+   Does not wait for the members' pending work (lbm_batch_run orders after it).
+   Errors: LBM_EINVAL if a context is NULL or repeated, members differ in device or storage,
+   a member is D3Q27, FP16 or has a population buffer of 4 GiB or more; LBM_ESTATE if a
+   member is not initialised or failed its health check; LBM_EDEVICE / LBM_ENOMEM from the
+   runtime (nothing is left allocated).                                                 */
 lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, int32_t steps_per_launch,
                             void* stream, lbm_batch** out);
 
@@ -219,7 +224,7 @@ lbm_status lbm_batch_run(lbm_batch* b, int64_t nlaunch);
    NULL is accepted.                                                                     */
 lbm_status lbm_batch_destroy(lbm_batch* b);
 
-/* Message of the last failed lbm_batch_* call.                                          */
+/* Message of the last failed lbm_batch_* call of the calling thread.                    */
 const char* lbm_batch_last_error(void);
 
 #ifdef __cplusplus

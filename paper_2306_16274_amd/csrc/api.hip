@@ -48,7 +48,7 @@ struct lbm_ctx {
     std::string err;
 };
 
-static std::string g_create_error;
+static thread_local std::string g_create_error;   // per calling thread
 static int default_fused_cfg(const lbm_ctx* c);
 
 static lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
@@ -970,7 +970,7 @@ struct lbm_batch {
     std::vector<hipEvent_t> ready;
 };
 
-static std::string g_batch_error;
+static thread_local std::string g_batch_error;    // per calling thread
 static lbm_status batch_fail(lbm_status s, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -1101,6 +1101,7 @@ extern "C" lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, int32_t 
     for (int i = 0; i < n; ++i) {
         const lbm_ctx* c = ctxs[i];
         if (!c) return batch_fail(LBM_EINVAL, "null context");
+        if (c->device != ctxs[0]->device) return batch_fail(LBM_EINVAL, "members must share a device");
         if (c->Q != 19) return batch_fail(LBM_EINVAL, "batched stepping supports D3Q19");
         if (c->p.storage != storage || storage == LBM_FP16)
             return batch_fail(LBM_EINVAL, "members must share FP32 or FP64 storage");
