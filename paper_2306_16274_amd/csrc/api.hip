@@ -28,6 +28,7 @@ struct lbm_ctx {
     int cur = 0;
     void* psi = nullptr;           // float64 (FP64 storage) or float32
     uint8_t* solid = nullptr;
+    uint32_t* links = nullptr;     // link words of the fused step (cylinder geometries)
     bool any_solid = false;
     double* mom = nullptr;         // rho, u (3), p: 5 N doubles, allocated on first use
     double* partial = nullptr;     // per-block partial sums (moments and health check)
@@ -213,7 +214,8 @@ extern "C" int64_t lbm_footprint_bytes(const lbm_params* p) {
     const int Q = p->lattice == 27 ? 27 : 19;
     const size_t b = storage_bytes(p->storage);
     const size_t r = p->storage == LBM_FP64 ? 8 : 4;
-    return (int64_t)(2 * Q * plane_stride(N) * b + N * r + N);
+    const size_t links = p->cylinder ? 4 : 0;     // link words of the fused step
+    return (int64_t)(2 * Q * plane_stride(N) * b + N * r + N + N * links);
 }
 
 template <typename R>
@@ -340,6 +342,19 @@ static long long count_fluid(const lbm_params& p, bool& any_solid) {
     return fluid;
 }
 
+// Link words for the fused step on a solid mask (stream-ordered after the mask).
+static hipError_t build_links(lbm_ctx* c) {
+    if (c->links) return hipSuccess;
+    hipError_t e = dmalloc(c->stream, (void**)&c->links, (size_t)c->N * sizeof(uint32_t));
+    if (e != hipSuccess) return e;
+    const Launch L = node_launch(c);
+    if (c->Q == 27)
+        hipLaunchKernelGGL(k_build_links<27>, L.grid, L.block, 0, c->stream, c->links, c->solid, grid_of(c));
+    else
+        hipLaunchKernelGGL(k_build_links<19>, L.grid, L.block, 0, c->stream, c->links, c->solid, grid_of(c));
+    return hipGetLastError();
+}
+
 static void free_all(lbm_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
@@ -347,6 +362,7 @@ static void free_all(lbm_ctx* c) {
         for (void* b : c->f) dfree(c->stream, b);
         dfree(c->stream, c->psi);
         dfree(c->stream, c->solid);
+        dfree(c->stream, c->links);
         dfree(c->stream, c->mom);
         dfree(c->stream, c->partial);
         dfree(c->stream, c->dtot);
@@ -401,6 +417,7 @@ extern "C" lbm_status lbm_create(const lbm_params* pp, lbm_ctx** out) {
                            pp->cylinder, pp->cyl_y, pp->cyl_z, pp->cyl_r);
         CHK(hipGetLastError());
     }
+    if (geom_of(c) == GEOM_MASK) CHK(build_links(c));
     CHK(dmalloc(c->stream, (void**)&c->dtot, 8 * sizeof(double)));
     CHK(hipHostMalloc((void**)&c->hhealth, 2 * sizeof(double), hipHostMallocDefault));
     CHK(hipEventCreateWithFlags(&c->health_ev, hipEventDisableTiming));
@@ -541,7 +558,7 @@ static void launch_fused_cfg(lbm_ctx* c, const void* fin, void* fout) {
     with_geom_nts(c, hints, [&](auto geom, auto nts) {
         hipLaunchKernelGGL((k_step_fused<Q, T, decltype(geom)::value, TX, TY, FULLX,
                                          decltype(nts)::value>),
-                           grid, block, 0, c->stream, (const T*)fin, (T*)fout, c->solid,
+                           grid, block, 0, c->stream, (const T*)fin, (T*)fout, c->links,
                            grid_of(c), P, ntx, nty, zc, remap, hints);
     });
 }
@@ -562,7 +579,7 @@ static void launch_fused_pf(lbm_ctx* c, const void* fin, void* fout) {
         with_geom_nts(c, hints, [&](auto geom, auto nts) {
             hipLaunchKernelGGL((k_step_fused_pf64<Q, decltype(geom)::value, TX, TY,
                                                   decltype(nts)::value>),
-                               grid, block, 0, c->stream, f0, f1, c->solid, grid_of(c), c->pd, zc,
+                               grid, block, 0, c->stream, f0, f1, c->links, grid_of(c), c->pd, zc,
                                remap, hints);
         });
     } else if constexpr ((sizeof(T) == 4 || sizeof(T) == 2) && fused_pf_lds_bytes(Q, TX, TY) <= kLdsBytesPerCU) {
@@ -574,7 +591,7 @@ static void launch_fused_pf(lbm_ctx* c, const void* fin, void* fout) {
         with_geom_nts(c, hints, [&](auto geom, auto nts) {
             hipLaunchKernelGGL((k_step_fused_pf<Q, T, decltype(geom)::value, TX, TY,
                                                 decltype(nts)::value>),
-                               grid, block, 0, c->stream, (const T*)fin, (T*)fout, c->solid,
+                               grid, block, 0, c->stream, (const T*)fin, (T*)fout, c->links,
                                grid_of(c), c->pf, zc, remap, hints);
         });
     } else {
@@ -1029,7 +1046,7 @@ static lbm_status build_tables(lbm_batch* b) {
             DomainDesc<T> d{};
             d.fin = (const T*)c->f[(c->cur + par) & 1];
             d.fout = (T*)c->f[(c->cur + par + 1) & 1];
-            d.solid = c->solid;
+            d.links = c->links;
             d.g = grid_of(c);
             d.P = P;
             d.ntx = ntx; d.nty = nty; d.zc = zc; d.block0 = (int)block0;
@@ -1128,6 +1145,9 @@ extern "C" lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, int32_t 
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
     b->ready.assign(n, nullptr);
     for (int i = 0; e == hipSuccess && i < n; ++i) e = hipEventCreateWithFlags(&b->ready[i], hipEventDisableTiming);
+    // a batch on the solid mask reads every member's link words (members without a
+    // cylinder get them here, from their wall mask)
+    for (int i = 0; e == hipSuccess && b->geom == GEOM_MASK && i < n; ++i) e = build_links(ctxs[i]);
     if (e != hipSuccess) { batch_fail(LBM_EDEVICE, "batch setup failed: %s", hipGetErrorString(e)); return bail(LBM_EDEVICE); }
     lbm_status st = storage == LBM_FP64 ? build_tables<double>(b) : build_tables<float>(b);
     if (st != LBM_OK) return bail(st);

@@ -175,49 +175,48 @@ struct WallBits { unsigned wx, wy, wz; };
 
 // Element index of the pull source x - e_i of population i for a column whose 3x3
 // in-plane neighbour indices are xy[(dy+1)*3 + dx+1] and whose plane indices are
-// zo[dz+1]; with bounce-back from the node itself when the source is solid.
+// zo[dz+1]; with bounce-back from the node itself when the source is solid. lk: the node's
+// link word (GEOM_MASK; bit i set when x - e_i is solid).
 template <int Q, int GEOM>
-__device__ __forceinline__ void pull_source(int i, const int* xy, const int* zo,
-                                            const uint8_t* __restrict__ solid,
+__device__ __forceinline__ void pull_source(int i, const int* xy, const int* zo, unsigned lk,
                                             const WallBits& wb, int& e, int& pop) {
     const int ex = vel_x(i), ey = vel_y(i), ez = vel_z(i);
     e = xy[(1 - ey) * 3 + (1 - ex)] + zo[1 - ez];
     pop = i;
     bool s = false;
-    if (GEOM == GEOM_MASK && i != 0) s = solid[e];
+    if (GEOM == GEOM_MASK && i != 0) s = (lk >> i) & 1u;
     if (GEOM == GEOM_WALLS && i != 0)
         s = ((wb.wx >> (1 - ex)) | (wb.wy >> (1 - ey)) | (wb.wz >> (1 - ez))) & 1u;
     if (s) { e = xy[4] + zo[1]; pop = opposite(i); }
 }
 
+// Link word of node n for the solid mask (bit 0: the node is solid; bit i: its neighbour
+// x - e_i is solid), 0 without a mask: one 4-byte load replaces a byte load per population.
 template <int GEOM>
-__device__ __forceinline__ bool node_solid(const uint8_t* __restrict__ solid, int n,
+__device__ __forceinline__ unsigned link_word(const uint32_t* __restrict__ links, int n) {
+    if constexpr (GEOM == GEOM_MASK) return links[n];
+    return 0u;
+}
+
+template <int GEOM>
+__device__ __forceinline__ bool node_solid(const uint32_t* __restrict__ links, int n,
                                            const WallBits& wb) {
-    if (GEOM == GEOM_MASK) return solid[n] != 0;
+    if (GEOM == GEOM_MASK) return links[n] & 1u;
     if (GEOM == GEOM_WALLS) return ((wb.wx | wb.wy | wb.wz) >> 1) & 1u;
     return false;
 }
 
-// Issue the Q loads of a column's node (values land in v[]). SPLIT keeps the plane's byte
-// offset apart from the node's (the compiler then selects the plane base per lane and
-// addresses in 64 bits); the plain tiles take it with the solid mask and 2- or 4-byte
-// storage: measured on the cylinder workloads, ms per step, D3Q27 320 x 256 x 192 FP32 1.71
-// vs 1.95, FP16 1.50 vs 2.00, 256 x 256 x 192 FP16 1.36 vs 1.75; FP64 is slower that way
-// (2.96 vs 2.58 at 256 wide) and so are the prefetching tiles' lead-in pulls (D3Q19 FP32
-// 0.489 vs 0.479).
-template <int Q, typename T, typename R, int GEOM, bool SPLIT = (GEOM == GEOM_MASK && sizeof(T) < 8)>
-__device__ __forceinline__ void pull_loads(const T* __restrict__ f, const uint8_t* __restrict__ solid,
+// Issue the Q loads of a column's node (values land in v[]).
+template <int Q, typename T, typename R, int GEOM>
+__device__ __forceinline__ void pull_loads(const T* __restrict__ f, const uint32_t* __restrict__ links,
                                            const int* xy, const int* zo, const WallBits& wb,
                                            unsigned pst, R* v) {
+    const unsigned lk = link_word<GEOM>(links, xy[4] + zo[1]);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         int e, pop;
-        pull_source<Q, GEOM>(i, xy, zo, solid, wb, e, pop);
-        if constexpr (SPLIT)
-            v[i] = static_cast<R>(*reinterpret_cast<const T*>(
-                reinterpret_cast<const char*>(f) + (size_t)pop * pst + (unsigned)e * (unsigned)sizeof(T)));
-        else
-            v[i] = static_cast<R>(ld_off(f, (unsigned)e * (unsigned)sizeof(T) + (unsigned)pop * pst));
+        pull_source<Q, GEOM>(i, xy, zo, lk, wb, e, pop);
+        v[i] = static_cast<R>(ld_off(f, (unsigned)e * (unsigned)sizeof(T) + (unsigned)pop * pst));
     }
 }
 
@@ -236,7 +235,7 @@ __device__ __forceinline__ R sum_q(const R* v) {
 // multi-domain (batched) kernel.
 template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX, bool NTS>
 __device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restrict__ fout,
-                                           const uint8_t* __restrict__ solid, const Grid& g,
+                                           const uint32_t* __restrict__ links, const Grid& g,
                                            const Phys<typename Arith<T>::type>& P,
                                            int t, int ntx, int nty, int zc, int hints) {
     using R = typename Arith<T>::type;
@@ -303,10 +302,10 @@ __device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restr
         zoffs(zp, zo);
         const WallBits wb{wh.wx, wh.wy, zbits(zp)};
         R hv;
-        if (node_solid<GEOM>(solid, hxy[4] + zo[1], wb)) hv = R(-1);
+        if (node_solid<GEOM>(links, hxy[4] + zo[1], wb)) hv = R(-1);
         else {
             R v[Q];
-            pull_loads<Q, T, R, GEOM>(fin, solid, hxy, zo, wb, pst, v);
+            pull_loads<Q, T, R, GEOM>(fin, links, hxy, zo, wb, pst, v);
             hv = psi_of(sum_q<Q, R>(v));
         }
         ring[slot][hy + 1][hx + OX] = hv;
@@ -316,8 +315,8 @@ __device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restr
         int zo[3];
         zoffs(zp, zo);
         const WallBits wb{wo.wx, wo.wy, zbits(zp)};
-        const bool s = node_solid<GEOM>(solid, oxy[4] + zo[1], wb);
-        pull_loads<Q, T, R, GEOM>(fin, solid, oxy, zo, wb, pst, v);
+        const bool s = node_solid<GEOM>(links, oxy[4] + zo[1], wb);
+        pull_loads<Q, T, R, GEOM>(fin, links, oxy, zo, wb, pst, v);
         ring[slot][ly + 1][lx + OX] = s ? R(-1) : psi_of(sum_q<Q, R>(v));
     };
     // LDS column of tile column lx + dx
@@ -434,7 +433,7 @@ __device__ __forceinline__ float pf_value<_Float16, float>(uint32_t v) {
 
 template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX, bool NTS>
 __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __restrict__ fout,
-                                              const uint8_t* __restrict__ solid, const Grid& g,
+                                              const uint32_t* __restrict__ links, const Grid& g,
                                               const Phys<float>& P, int t, int ntx, int nty,
                                               int zc, int hints) {
     static_assert(sizeof(T) == 4 || sizeof(T) == 2, "the LDS prefetch moves 2- or 4-byte elements");
@@ -513,8 +512,8 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
         int zo[3];
         zoffs(zp, zo);
         const WallBits wb{wo.wx, wo.wy, zbits(zp)};
-        const bool s = node_solid<GEOM>(solid, oxy[4] + zo[1], wb);
-        pull_loads<Q, T, R, GEOM, false>(fin, solid, oxy, zo, wb, pst, v);
+        const bool s = node_solid<GEOM>(links, oxy[4] + zo[1], wb);
+        pull_loads<Q, T, R, GEOM>(fin, links, oxy, zo, wb, pst, v);
         ring[slot][ly + 1][lx + OX] = s ? R(-1) : psi_of(sum_q<Q, R>(v));
     };
     auto halo_psi = [&](int zp, int slot) {
@@ -523,10 +522,10 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
         zoffs(zp, zo);
         const WallBits wb{wh.wx, wh.wy, zbits(zp)};
         R hv;
-        if (node_solid<GEOM>(solid, hxy[4] + zo[1], wb)) hv = R(-1);
+        if (node_solid<GEOM>(links, hxy[4] + zo[1], wb)) hv = R(-1);
         else {
             R v[Q];
-            pull_loads<Q, T, R, GEOM, false>(fin, solid, hxy, zo, wb, pst, v);
+            pull_loads<Q, T, R, GEOM>(fin, links, hxy, zo, wb, pst, v);
             hv = psi_of(sum_q<Q, R>(v));
         }
         ring[slot][hy + 1][hx + OX] = hv;
@@ -540,11 +539,12 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
         int zo[3];
         zoffs(zp, zo);
         const WallBits wb{wo.wx, wo.wy, zbits(zp)};
+        const unsigned lk = link_word<GEOM>(links, oxy[4] + zo[1]);
         if (interior_row) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 int e, pop;
-                pull_source<Q, GEOM>(i, oxy, zo, solid, wb, e, pop);
+                pull_source<Q, GEOM>(i, oxy, zo, lk, wb, e, pop);
                 lds_dma<(int)sizeof(T), 2>(
                     reinterpret_cast<const char*>(fin) + ((unsigned)e * (unsigned)sizeof(T) + (unsigned)pop * pst),
                     &pf_own[i][wave * 64]);
@@ -553,7 +553,7 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 int e, pop;
-                pull_source<Q, GEOM>(i, oxy, zo, solid, wb, e, pop);
+                pull_source<Q, GEOM>(i, oxy, zo, lk, wb, e, pop);
                 lds_dma<(int)sizeof(T), 0>(
                     reinterpret_cast<const char*>(fin) + ((unsigned)e * (unsigned)sizeof(T) + (unsigned)pop * pst),
                     &pf_own[i][wave * 64]);
@@ -565,10 +565,11 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
         int zo[3];
         zoffs(zp, zo);
         const WallBits hb{wh.wx, wh.wy, zbits(zp)};
+        const unsigned lk = link_word<GEOM>(links, hxy[4] + zo[1]);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             int e, pop;
-            pull_source<Q, GEOM>(i, hxy, zo, solid, hb, e, pop);
+            pull_source<Q, GEOM>(i, hxy, zo, lk, hb, e, pop);
             lds_dma<(int)sizeof(T), 0>(
                 reinterpret_cast<const char*>(fin) + ((unsigned)e * (unsigned)sizeof(T) + (unsigned)pop * pst),
                 &pf_halo[i][wave * 64]);
@@ -581,7 +582,7 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
         zoffs(zp, zo);
         const WallBits hb{wh.wx, wh.wy, zbits(zp)};
         R hv;
-        if (node_solid<GEOM>(solid, hxy[4] + zo[1], hb)) hv = R(-1);
+        if (node_solid<GEOM>(links, hxy[4] + zo[1], hb)) hv = R(-1);
         else {
             R s = 0;
 #pragma unroll
@@ -597,7 +598,7 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
 #pragma unroll
         for (int i = 0; i < Q; ++i) v[i] = pf_value<T, R>(pf_own[i][tid]);
         ring[slot][ly + 1][lx + OX] =
-            node_solid<GEOM>(solid, oxy[4] + zo[1], wb) ? R(-1) : psi_of(sum_q<Q, R>(v));
+            node_solid<GEOM>(links, oxy[4] + zo[1], wb) ? R(-1) : psi_of(sum_q<Q, R>(v));
     };
 
     R cur[Q], nxt[Q];
@@ -662,7 +663,7 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
 template <int Q, int GEOM, int TX, int TY, bool NTS>
 __device__ __forceinline__ void fused_tile_pf64(const double* __restrict__ fin,
                                                 double* __restrict__ fout,
-                                                const uint8_t* __restrict__ solid, const Grid& g,
+                                                const uint32_t* __restrict__ links, const Grid& g,
                                                 const Phys<double>& P, int t, int nty, int zc,
                                                 int hints) {
     using R = double;
@@ -719,8 +720,8 @@ __device__ __forceinline__ void fused_tile_pf64(const double* __restrict__ fin,
         int zo[3];
         zoffs(zp, zo);
         const WallBits wb{wo.wx, wo.wy, zbits(zp)};
-        const bool s = node_solid<GEOM>(solid, oxy[4] + zo[1], wb);
-        pull_loads<Q, T, R, GEOM>(fin, solid, oxy, zo, wb, pst, v);
+        const bool s = node_solid<GEOM>(links, oxy[4] + zo[1], wb);
+        pull_loads<Q, T, R, GEOM>(fin, links, oxy, zo, wb, pst, v);
         ring[slot][ly + 1][lx] = s ? R(-1) : psi_of(sum_q<Q, R>(v));
     };
     auto halo_psi = [&](int zp, int slot) {
@@ -729,10 +730,10 @@ __device__ __forceinline__ void fused_tile_pf64(const double* __restrict__ fin,
         zoffs(zp, zo);
         const WallBits wb{wh.wx, wh.wy, zbits(zp)};
         R hv;
-        if (node_solid<GEOM>(solid, hxy[4] + zo[1], wb)) hv = R(-1);
+        if (node_solid<GEOM>(links, hxy[4] + zo[1], wb)) hv = R(-1);
         else {
             R v[Q];
-            pull_loads<Q, T, R, GEOM>(fin, solid, hxy, zo, wb, pst, v);
+            pull_loads<Q, T, R, GEOM>(fin, links, hxy, zo, wb, pst, v);
             hv = psi_of(sum_q<Q, R>(v));
         }
         ring[slot][hy + 1][hx] = hv;
@@ -741,10 +742,11 @@ __device__ __forceinline__ void fused_tile_pf64(const double* __restrict__ fin,
         int zo[3];
         zoffs(zp, zo);
         const WallBits wb{wo.wx, wo.wy, zbits(zp)};
+        const unsigned lk = link_word<GEOM>(links, oxy[4] + zo[1]);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             int e, pop;
-            pull_source<Q, GEOM>(i, oxy, zo, solid, wb, e, pop);
+            pull_source<Q, GEOM>(i, oxy, zo, lk, wb, e, pop);
             const char* src = reinterpret_cast<const char*>(fin) + ((unsigned)e * 8u + (unsigned)pop * pst);
             lds_dma<4, 0>(src, &pf_lo[i][wave * 64]);
             lds_dma<4, 0>(src + 4, &pf_hi[i][wave * 64]);
@@ -758,7 +760,7 @@ __device__ __forceinline__ void fused_tile_pf64(const double* __restrict__ fin,
         for (int i = 0; i < Q; ++i)
             v[i] = __builtin_bit_cast(double, ((unsigned long long)pf_hi[i][tid] << 32) | pf_lo[i][tid]);
         ring[slot][ly + 1][lx] =
-            node_solid<GEOM>(solid, oxy[4] + zo[1], wb) ? R(-1) : psi_of(sum_q<Q, R>(v));
+            node_solid<GEOM>(links, oxy[4] + zo[1], wb) ? R(-1) : psi_of(sum_q<Q, R>(v));
     };
 
     R cur[Q], nxt[Q];
@@ -804,21 +806,21 @@ __device__ __forceinline__ void fused_tile_pf64(const double* __restrict__ fin,
 template <int Q, int GEOM, int TX, int TY, bool NTS>
 __global__ __launch_bounds__(TX * TY) void k_step_fused_pf64(const double* __restrict__ fin,
                                                             double* __restrict__ fout,
-                                                            const uint8_t* __restrict__ solid,
+                                                            const uint32_t* __restrict__ links,
                                                             Grid g, Phys<double> P, int zc,
                                                             int remap, int hints) {
     const int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    fused_tile_pf64<Q, GEOM, TX, TY, NTS>(fin, fout, solid, g, P, t, (g.ny + TY - 1) / TY, zc, hints);
+    fused_tile_pf64<Q, GEOM, TX, TY, NTS>(fin, fout, links, g, P, t, (g.ny + TY - 1) / TY, zc, hints);
 }
 
 template <int Q, typename T, int GEOM, int TX, int TY, bool NTS>
 __global__ __launch_bounds__(TX * TY) void k_step_fused_pf(const T* __restrict__ fin,
                                                           T* __restrict__ fout,
-                                                          const uint8_t* __restrict__ solid,
+                                                          const uint32_t* __restrict__ links,
                                                           Grid g, Phys<float> P, int zc,
                                                           int remap, int hints) {
     const int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    fused_tile_pf<Q, T, GEOM, TX, TY, true, NTS>(fin, fout, solid, g, P, t, 1,
+    fused_tile_pf<Q, T, GEOM, TX, TY, true, NTS>(fin, fout, links, g, P, t, 1,
                                                  (g.ny + TY - 1) / TY, zc, hints);
 }
 
@@ -827,12 +829,12 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_pf(const T* __restrict__
 template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX, bool NTS>
 __global__ __launch_bounds__(TX * TY) void k_step_fused(const T* __restrict__ fin,
                                                        T* __restrict__ fout,
-                                                       const uint8_t* __restrict__ solid,
+                                                       const uint32_t* __restrict__ links,
                                                        Grid g, Phys<typename Arith<T>::type> P,
                                                        int ntx, int nty, int zc, int remap,
                                                        int hints) {
     const int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    fused_tile<Q, T, GEOM, TX, TY, FULLX, NTS>(fin, fout, solid, g, P, t, ntx, nty, zc, hints);
+    fused_tile<Q, T, GEOM, TX, TY, FULLX, NTS>(fin, fout, links, g, P, t, ntx, nty, zc, hints);
 }
 
 // One domain of a batched step: its buffers, geometry, physics and the first workgroup
@@ -841,7 +843,7 @@ template <typename T>
 struct DomainDesc {
     const T* fin;
     T* fout;
-    const uint8_t* solid;
+    const uint32_t* links;     // link words (solid mask only)
     Grid g;
     Phys<typename Arith<T>::type> P;
     int ntx, nty, zc, block0;
@@ -859,7 +861,7 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_batch(const DomainDesc<T
         if (d[mid].block0 <= b) lo = mid; else hi = mid - 1;
     }
     const DomainDesc<T>& D = d[lo];
-    fused_tile<Q, T, GEOM, TX, TY, false, NTS>(D.fin, D.fout, D.solid, D.g, D.P, b - D.block0,
+    fused_tile<Q, T, GEOM, TX, TY, false, NTS>(D.fin, D.fout, D.links, D.g, D.P, b - D.block0,
                                                D.ntx, D.nty, D.zc, 0);
 }
 
@@ -874,7 +876,7 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_batch_pf(const DomainDes
         if (d[mid].block0 <= b) lo = mid; else hi = mid - 1;
     }
     const DomainDesc<T>& D = d[lo];
-    fused_tile_pf<Q, T, GEOM, TX, TY, false, NTS>(D.fin, D.fout, D.solid, D.g, D.P, b - D.block0,
+    fused_tile_pf<Q, T, GEOM, TX, TY, false, NTS>(D.fin, D.fout, D.links, D.g, D.P, b - D.block0,
                                                   D.ntx, D.nty, D.zc, 0);
 }
 

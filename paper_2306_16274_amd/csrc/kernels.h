@@ -426,4 +426,23 @@ __global__ __launch_bounds__(256) void k_build_solid(uint8_t* __restrict__ solid
     solid[x + (long long)g.nx * (y + (long long)g.ny * z)] = s ? 1 : 0;
 }
 
+// Link words of the fused step on the solid mask: bit 0 = node n is solid, bit i (1..Q-1)
+// = its neighbour x - e_i (periodically wrapped, as the fused kernels wrap) is solid.
+template <int Q>
+__global__ __launch_bounds__(256) void k_build_links(uint32_t* __restrict__ links,
+                                                     const uint8_t* __restrict__ solid, Grid g) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    auto wrap = [](int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); };
+    const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
+    uint32_t w = solid[n] ? 1u : 0u;
+    for (int i = 1; i < Q; ++i) {
+        const int xs = wrap(x - vel_x(i), g.nx), ys = wrap(y - vel_y(i), g.ny), zs = wrap(z - vel_z(i), g.nz);
+        if (solid[xs + (long long)g.nx * (ys + (long long)g.ny * zs)]) w |= 1u << i;
+    }
+    links[n] = w;
+}
+
 }  // namespace lbmk

@@ -58,6 +58,9 @@ def test_host_only_entry_points_without_gpu():
     p = lbm.lbm_params_default()
     assert p.lattice == 19 and p.nx == 64
     assert lbm.lbm_footprint_bytes(p) == 2 * 19 * 64 ** 3 * 4 + 64 ** 3 * 4 + 64 ** 3
+    p.cylinder = 1                # the fused step's link words: 4 more bytes per node
+    assert lbm.lbm_footprint_bytes(p) == 2 * 19 * 64 ** 3 * 4 + 64 ** 3 * 4 + 64 ** 3 * 5
+    p.cylinder = 0
     rv, rl = lbm.lbm_coexistence(p)
     assert 0.009 < rv < 0.0095 and 0.355 < rl < 0.36
     bad = lbm.lbm_params_default()
