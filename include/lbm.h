@@ -136,8 +136,8 @@ lbm_status lbm_get_populations(lbm_ctx* c, double* f);
    context stream and returns without waiting, except every reduce_every steps, where the
    result of the previous health check is read. nsteps >= 0.
    The launch configuration of the fused step (tile shape: full rows for nx = 256, 320 or
-   384, else 32x8 tiles; z-chunk length; nontemporal hints) is chosen from the domain width,
-   the storage type and the lattice. For tuning, the environment variables
+   384, else 64x8 or 64x4 tiles; z-chunk length; nontemporal hints) is chosen from the
+   domain width, the storage type and the lattice. For tuning, the environment variables
    LBM_FUSED_CONFIG, LBM_FUSED_ZC, LBM_FUSED_REMAP and LBM_FUSED_HINTS override it; every
    configuration gives bitwise the same populations.                                   */
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps);

@@ -496,7 +496,7 @@ static const char* const kTwoPassNames[] = {"k_density_psi", "k_collide"};
 static const char* const kFusedNames[] = {"k_step_fused"};
 
 // Tile configurations of the fused kernel. 256 x 2 full rows: the x-shifted pulls of a
-// row stay inside one workgroup and the halo is two rows; 32 x 8 tiles for other widths.
+// row stay inside one workgroup and the halo is two rows; 64x8 or 64x4 tiles for other widths.
 
 static int default_fused_cfg(const lbm_ctx* c) {
     if (const char* e = getenv("LBM_FUSED_CONFIG")) {      // tuning override
@@ -622,6 +622,8 @@ static void launch_fused(lbm_ctx* c, const void* fin, void* fout) {
     case 3: launch_fused_pf<Q, T, 256, 4>(c, fin, fout); break;
     case 4: launch_fused_pf<Q, T, 256, 2>(c, fin, fout); break;
     case 5: case 6: case 7: case 8: launch_fused_wide<Q, T>(c, fin, fout); break;
+    case 9: launch_fused_cfg<Q, T, 64, 4, false>(c, fin, fout); break;
+    case 10: launch_fused_cfg<Q, T, 64, 8, false>(c, fin, fout); break;
     default: launch_fused_cfg<Q, T, 32, 8, false>(c, fin, fout); break;
     }
 }

@@ -45,7 +45,8 @@ constexpr int kHintNtStore = 1, kHintNtInterior = 2;
 // Launch configurations of the fused step: tile width and height, whether the tile spans
 // the whole x row (then nx must equal tx), and pf: the next planes are prefetched into LDS
 // (k_step_fused_pf; 2- or 4-byte storage, and the populations of a tile plus its halo rows
-// must fit in LDS). Full rows of 256, 320 and 384 nodes; 32x8 tiles serve other widths.
+// must fit in LDS). Full rows of 256, 320 and 384 nodes; 64x8 (4-byte storage) or 64x4
+// tiles serve other widths (32x8 tiles remain as configuration 0).
 // Full-row tiles cut z into chunks sized for whole rounds of one workgroup per CU (each holds
 // a CU alone: LDS or VGPRs), so every workgroup marches as far as possible and the two
 // lead-in planes of a chunk are paid rarely; small tiles march through 16-plane chunks. Both
@@ -55,7 +56,8 @@ constexpr FusedCfg kFusedCfgs[] = {{32, 8, false, false}, {256, 2, true, false},
                                    {256, 4, true, false}, {256, 4, true, true},
                                    {256, 2, true, true},  {320, 2, true, false},
                                    {320, 2, true, true},  {384, 2, true, false},
-                                   {384, 2, true, true}};
+                                   {384, 2, true, true},  {64, 4, false, false},
+                                   {64, 8, false, false}};
 constexpr int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
 constexpr int kFusedZcTiled = 16, kFusedZcMin = 8;
 
@@ -117,17 +119,22 @@ constexpr int default_fused_hints(const FusedCfg& c, int elem_bytes) {
 //     D3Q27 (2.29-2.33; 64: 2.36 vs 2.56 plain, 4.10 plain 256x4);
 //   2-byte storage: prefetching 256x4 for D3Q19 (0.320 vs 0.342 plain), plain 256x2 for
 //     D3Q27 (0.602-0.609 vs 0.645 prefetching; 64: 0.92 plain 256x4).
+// Other widths (GLUPS; 32x8 / 64x4 / 64x8 / 128x4 tiles): 300^2 x 250 D3Q19 FP32 17.4 / 21.8 /
+// 23.3 / 22.5, D3Q27 FP32 13.0 / 14.7 / 14.9 / 13.7, D3Q27 FP16 19.5 / 23.1 / 20.5 / 19.3,
+// D3Q27 FP32 with walls 12.7 / 13.8 / 14.5 / 13.9; 200^3 D3Q19 FP32 17.4 / 18.7 / 18.2 / 20.0;
+// FP64 384^2 x 160 D3Q19 12.3 / 12.9 / 12.9 / 12.5, 320 x 256 x 192 D3Q27 cylinder 6.0 / 6.4 /
+// 6.2 / 5.6: 64x8 for 4-byte storage, 64x4 otherwise.
 // 320- and 384-wide domains (GLUPS; 2-row full-row tiles vs 32x8 tiles): D3Q19 prefetching
 // (FP32 384^2 x 192 30.0 vs 22.0, 27.3 plain; 320 x 256 x 192 28.6 vs 22.2; FP16 384^2 x 192
 // 43-45 vs 30.7), D3Q27 plain (320 x 256 x 192 FP32 19.3 vs 15.5, 19.3 prefetching, which
-// spills; FP16 28.1 vs 21.5); FP64 stays on 32x8 tiles (12.3-12.7 vs 9.4 at 384^2 x 160,
+// spills; FP16 28.1 vs 21.5); FP64 takes 64x4 tiles (32x8: 12.3-12.7 vs 9.4 at 384^2 x 160,
 // 6.7-7.1 vs 5.4-5.6 for D3Q27 at 320 x 256 x 192: 640 or 768 threads leave too few VGPRs).
 constexpr int default_fused_cfg_index(int nx, int elem_bytes, int Q) {
     return (nx == 320 || nx == 384)
-               ? (elem_bytes == 8 ? 0
+               ? (elem_bytes == 8 ? 9
                   : Q == 19 && fused_pf_lds_bytes(Q, nx, 2) <= kLdsBytesPerCU ? (nx == 320 ? 6 : 8)
                   : (nx == 320 ? 5 : 7))
-         : nx != 256 ? 0
+         : nx != 256 ? (elem_bytes == 4 ? 10 : 9)
          : elem_bytes == 8 ? (Q == 27 && fused_pf64_lds_bytes(Q, 256, 2) <= kLdsBytesPerCU ? 4 : 1)
          : elem_bytes == 4 ? (fused_pf_lds_bytes(Q, 256, 4) <= kLdsBytesPerCU ? 3
                               : fused_pf_lds_bytes(Q, 256, 2) <= kLdsBytesPerCU ? 4 : 1)

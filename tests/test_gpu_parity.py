@@ -263,7 +263,7 @@ def test_full_size_256_sampled_windows(L, storage):
 def test_fused_prefetch_tiles_bitwise_equal_plain_tiles(L, monkeypatch, geom, Q, storage):
     """Full-row tiles with the LDS prefetch (launch configurations 3 = 256x4 and 4 = 256x2,
     the 256-wide FP32 defaults) against plain full-row tiles (2 = 256x4, 1 = 256x2) and the
-    32x8 tiles (0): the per-node arithmetic is the same, so the populations agree bit for
+    32x8, 64x4 and 64x8 tiles (0, 9, 10): the per-node arithmetic is the same, so the populations agree bit for
     bit. Ragged y extent (10 rows of 4-row tiles) and several z-chunks (LBM_FUSED_ZC = 7
     over nz = 20). D3Q27 does not fit the 256x4 prefetch buffers and runs plain 256x4 tiles
     under configuration 3. Each configuration also runs with the other store hint
@@ -276,8 +276,8 @@ def test_fused_prefetch_tiles_bitwise_equal_plain_tiles(L, monkeypatch, geom, Q,
     rv, rl = maxwell(w)
     out = {}
     monkeypatch.setenv("LBM_FUSED_ZC", "7")
-    runs = [(c, None) for c in ("3", "4", "2", "1", "0")] + [(c, h) for c in ("3", "4", "1", "0")
-                                                              for h in ("0", "1")]
+    runs = [(c, None) for c in ("3", "4", "2", "1", "0", "9", "10")] + [
+        (c, h) for c in ("3", "4", "1", "0") for h in ("0", "1")]
     for cfg, hints in runs:
         monkeypatch.setenv("LBM_FUSED_CONFIG", cfg)
         if hints is None:
@@ -401,7 +401,7 @@ def test_full_size_cylinder_d3q27_sampled_windows(L, storage):
     z = 191, cylinder of radius 20 along x resting on the wall, CS at 0.6 T_c, R = 30
     falling at 0.04, wetting G_ads = 0.2): one GPU step against the oracle on windows on the
     cylinder surface, the wall, the droplet and random places, each storage in its default
-    launch configuration (FP32 and FP16: plain 320x2 full-row tiles; FP64: 32x8 tiles).
+    launch configuration (FP32 and FP16: plain 320x2 full-row tiles; FP64: 64x4 tiles).
     FP64 to 1e-12 relative in rho; FP32 shifted storage to 1e-6; FP16 shifted storage
     reported (bound 5e-3)."""
     w = si.CYLINDER_D3Q27
