@@ -189,7 +189,9 @@ lbm_status lbm_synchronize(lbm_ctx* c);
    of the equation of state described by *p. Host-only.                                 */
 lbm_status lbm_coexistence(const lbm_params* p, double* rho_v, double* rho_l);
 
-/* Device bytes a context created from *p allocates (for admission control), or -1.    */
+/* Device bytes a context created from *p allocates (for admission control), or -1.
+   Includes the fused step's link words (4 bytes per node) when p has a cylinder; a batch
+   that contains a cylinder lattice adds them to its other members as well.            */
 int64_t lbm_footprint_bytes(const lbm_params* p);
 
 /*
