@@ -84,6 +84,7 @@ def run_gpu(w, storage, steps, warmup, rho_ref_choice="vapour", step_kernel="fus
     torch.cuda.set_stream(stream)
     p.stream = stream.cuda_stream
     assert p.stream, "expected a non-null HIP stream handle"
+    plan = L.lbm_fused_plan(p) if step_kernel == "fused" else None
     lat = L.Lattice(p)
     cx, cy, cz = w.droplet_centre()
     lat.init_droplet(cx, cy, cz, w.R, w.W, rho_l, rho_v, 0.0, 0.0, 0.0, w.noise, w.seed)
@@ -101,7 +102,7 @@ def run_gpu(w, storage, steps, warmup, rho_ref_choice="vapour", step_kernel="fus
     lat.close()
     torch.cuda.set_stream(torch.cuda.default_stream())
     return dict(ms=ms, ms_per_step=ms / steps, mlups=w.nodes * steps / (ms * 1e-3) / 1e6,
-                kernel_ms=ktimes, rho_ref=rho_ref, rho_v=rho_v, rho_l=rho_l,
+                kernel_ms=ktimes, rho_ref=rho_ref, rho_v=rho_v, rho_l=rho_l, plan=plan,
                 mass=float(mom["totals"][0]))
 
 
@@ -242,6 +243,7 @@ def main():
                  "storage": "fp16 shifted", "effective_GBs": round(eff16, 1),
                  "effective_frac": round(eff16 / HBM_PEAK_GBS, 4),
                  "kernel_ms": r16["kernel_ms"]},
+        "launch_plan": r32["plan"],
         "slab_of_8": slab,
         "effective_step_GBs": round(effective, 1),
         "effective_step_frac": round(effective / HBM_PEAK_GBS, 4),

@@ -194,6 +194,24 @@ lbm_status lbm_coexistence(const lbm_params* p, double* rho_v, double* rho_l);
    that contains a cylinder lattice adds them to its other members as well.            */
 int64_t lbm_footprint_bytes(const lbm_params* p);
 
+/* Launch plan of the fused step (step_kernel = LBM_STEP_FUSED) for a lattice created from
+   *p on a device with `cus` compute units (256 on MI355X): what lbm_step launches, chosen
+   from the width, the storage type and the lattice, with the LBM_FUSED_* environment
+   overrides applied as lbm_step applies them. Host-only. Errors: LBM_EINVAL for a NULL
+   argument, cus < 1 or parameters lbm_create would reject.                              */
+typedef struct {
+    int32_t config;       /* launch configuration index (LBM_FUSED_CONFIG)                 */
+    int32_t tile_x;       /* (x, y) columns of one workgroup: tile_x * tile_y threads       */
+    int32_t tile_y;
+    int32_t full_rows;    /* 1: a tile spans whole x rows (tile_x == nx)                    */
+    int32_t prefetch;     /* 1: the planes ahead are loaded into LDS asynchronously        */
+    int32_t z_chunk;      /* planes marched by one workgroup (LBM_FUSED_ZC)                 */
+    int32_t xcd_order;    /* 1: tiles mapped to XCDs in contiguous ranges (LBM_FUSED_REMAP) */
+    int32_t hints;        /* bit 0: nontemporal stores; bit 1: nontemporal interior loads  */
+    int64_t workgroups;   /* workgroups of one time step                                    */
+} lbm_fused_plan_t;
+lbm_status lbm_fused_plan(const lbm_params* p, int32_t cus, lbm_fused_plan_t* out);
+
 /*
  * Batched stepping (serving many independent lattices). A batch holds a fixed set of
  * contexts (D3Q19, all FP32 or all FP64 storage, each initialised) and advances all of

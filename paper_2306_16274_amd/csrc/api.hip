@@ -498,28 +498,71 @@ static const char* const kFusedNames[] = {"k_step_fused"};
 // Tile configurations of the fused kernel. 256 x 2 full rows: the x-shifted pulls of a
 // row stay inside one workgroup and the halo is two rows; 64x8 or 64x4 tiles for other widths.
 
-static int default_fused_cfg(const lbm_ctx* c) {
+// Launch configuration of the fused step for a lattice of width nx, element size elem and
+// lattice Q: the default of fused.h unless LBM_FUSED_CONFIG names a valid one (a full-row
+// configuration needs nx equal to its width; FP64 has no 320/384-wide instantiations).
+static int fused_cfg_for(int nx, int elem, int Q) {
     if (const char* e = getenv("LBM_FUSED_CONFIG")) {      // tuning override
         const int v = atoi(e);
-        if (v >= 0 && v < kNumFusedCfgs && (!kFusedCfgs[v].fullx || c->p.nx == kFusedCfgs[v].tx) &&
-            !(c->elem == 8 && kFusedCfgs[v].tx > 256))
+        if (v >= 0 && v < kNumFusedCfgs && (!kFusedCfgs[v].fullx || nx == kFusedCfgs[v].tx) &&
+            !(elem == 8 && kFusedCfgs[v].tx > 256))
             return v;
     }
-    return default_fused_cfg_index(c->p.nx, (int)c->elem, c->Q);
+    return default_fused_cfg_index(nx, elem, Q);
+}
+static int default_fused_cfg(const lbm_ctx* c) { return fused_cfg_for(c->p.nx, (int)c->elem, c->Q); }
+
+// Whether a configuration's prefetching tile fits in LDS for this lattice and element size
+// (the launch falls back to the plain tile of the same shape otherwise).
+static bool fused_prefetch_fits(const FusedCfg& f, int Q, int elem) {
+    if (!f.pf || !f.fullx) return false;
+    if (elem == 8) return fused_pf64_lds_bytes(Q, f.tx, f.ty) <= kLdsBytesPerCU;
+    return fused_pf_lds_bytes(Q, f.tx, f.ty) <= kLdsBytesPerCU;
 }
 
-// Planes per z-chunk and tile order (defaults of fused.h: about one workgroup per CU for
-// full-row tiles, XCD-contiguous tile ranges so that neighbouring rows share an L2).
+// Planes per z-chunk, tile order and cache hints of a launch (defaults of fused.h, then the
+// LBM_FUSED_* tuning overrides), and the workgroup count.
+struct FusedPlan { int zc, remap, hints; long long workgroups; };
+static FusedPlan fused_plan(const lbm_params& p, int elem, int cfg, int cus) {
+    const FusedCfg& f = kFusedCfgs[cfg];
+    const long long tiles = (long long)((p.nx + f.tx - 1) / f.tx) * ((p.ny + f.ty - 1) / f.ty);
+    FusedPlan pl;
+    pl.zc = default_fused_zc(f, tiles, p.nz, cus);
+    pl.remap = default_fused_remap(f);
+    pl.hints = default_fused_hints(f, elem);
+    if (const char* e = getenv("LBM_FUSED_HINTS")) pl.hints = atoi(e);         // tuning override
+    if (const char* e = getenv("LBM_FUSED_ZC")) pl.zc = std::max(1, atoi(e));   // tuning override
+    if (const char* e = getenv("LBM_FUSED_REMAP")) pl.remap = atoi(e) != 0;    // tuning override
+    pl.zc = std::min(pl.zc, p.nz);
+    pl.workgroups = tiles * ((p.nz + pl.zc - 1) / pl.zc);
+    return pl;
+}
 static void fused_chunking(const lbm_ctx* c, int& zc, int& remap, int& hints) {
-    const FusedCfg& f = kFusedCfgs[c->fused_cfg];
-    const long long tiles = (long long)((c->p.nx + f.tx - 1) / f.tx) * ((c->p.ny + f.ty - 1) / f.ty);
-    zc = default_fused_zc(f, tiles, c->p.nz, c->cus);
-    remap = default_fused_remap(kFusedCfgs[c->fused_cfg]);
-    hints = default_fused_hints(kFusedCfgs[c->fused_cfg], (int)c->elem);
-    if (const char* e = getenv("LBM_FUSED_HINTS")) hints = atoi(e);            // tuning override
-    if (const char* e = getenv("LBM_FUSED_ZC")) zc = std::max(1, atoi(e));      // tuning override
-    if (const char* e = getenv("LBM_FUSED_REMAP")) remap = atoi(e) != 0;       // tuning override
-    zc = std::min(zc, c->p.nz);
+    const FusedPlan pl = fused_plan(c->p, (int)c->elem, c->fused_cfg, c->cus);
+    zc = pl.zc;
+    remap = pl.remap;
+    hints = pl.hints;
+}
+
+extern "C" lbm_status lbm_fused_plan(const lbm_params* p, int32_t cus, lbm_fused_plan_t* out) {
+    if (!p || !out) return fail(nullptr, LBM_EINVAL, "null argument");
+    if (cus < 1) return fail(nullptr, LBM_EINVAL, "cus must be >= 1");
+    const lbm_status st = validate(*p);
+    if (st != LBM_OK) return st;
+    const int elem = (int)storage_bytes(p->storage), Q = p->lattice;
+    const int cfg = fused_cfg_for(p->nx, elem, Q);
+    const FusedCfg& f = kFusedCfgs[cfg];
+    const FusedPlan pl = fused_plan(*p, elem, cfg, cus);
+    out->config = cfg;
+    out->tile_x = f.tx;
+    out->tile_y = f.ty;
+    out->full_rows = f.fullx ? 1 : 0;
+    out->prefetch = fused_prefetch_fits(f, Q, elem) ? 1 : 0;
+    out->z_chunk = pl.zc;
+    out->xcd_order = pl.remap;
+    out->hints = pl.hints;
+    out->workgroups = pl.workgroups;
+    return LBM_OK;
 }
 
 // Calls f(geometry, store hint) with both as compile-time constants (std::integral_constant):

@@ -13,10 +13,12 @@
 //     plane z from the registers filled one iteration earlier, with psi(z-1..z+1) from
 //     LDS, and stores it;
 //   * the first H threads also pull the populations of the halo nodes of plane z+1,
-//     only to form their psi (H = 2(TX+TY)+4 for a tile, 2 TX for full rows). Those rows are pulled by the neighbouring tiles
-//     at about the same time: tiles are mapped to XCDs in contiguous ranges (workgroup b
-//     runs on XCD b mod 8), so neighbouring tiles share an L2 and the halo re-reads stay
-//     on chip;
+//     only to form their psi (H = 2(TX+TY)+4 for a tile, 2 TX for full rows). Those rows
+//     are pulled by the neighbouring tiles at about the same time: tiles are mapped to
+//     XCDs in contiguous ranges (workgroup b runs on XCD b mod 8), so neighbouring tiles
+//     share an L2 and the halo re-reads stay on chip;
+//   * with a cylinder, solidity comes from one 32-bit link word per node (bit 0: the node,
+//     bit i: its neighbour x - e_i), not from a byte load per population;
 //   * addresses are 32-bit byte offsets from the buffer base (the host checks that the
 //     population buffer is below 4 GiB), with the in-plane offsets of the 3x3 column
 //     neighbourhood computed once per thread.

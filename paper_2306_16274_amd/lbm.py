@@ -52,6 +52,12 @@ class lbm_params(ctypes.Structure):
     ]
 
 
+class lbm_fused_plan_t(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("config", "tile_x", "tile_y", "full_rows", "prefetch",
+                                               "z_chunk", "xcd_order", "hints")] + [
+        ("workgroups", ctypes.c_int64)]
+
+
 class LbmError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
@@ -82,6 +88,8 @@ _SIGS = {
     "lbm_coexistence": (ctypes.c_int, [ctypes.POINTER(lbm_params), ctypes.POINTER(_D),
                                        ctypes.POINTER(_D)]),
     "lbm_footprint_bytes": (ctypes.c_int64, [ctypes.POINTER(lbm_params)]),
+    "lbm_fused_plan": (ctypes.c_int, [ctypes.POINTER(lbm_params), ctypes.c_int32,
+                                      ctypes.POINTER(lbm_fused_plan_t)]),
     "lbm_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
     "lbm_batch_run": (ctypes.c_int, [_P, ctypes.c_int64]),
     "lbm_batch_destroy": (ctypes.c_int, [_P]),
@@ -224,6 +232,14 @@ def lbm_coexistence(params):
 
 def lbm_footprint_bytes(params):
     return library().lbm_footprint_bytes(ctypes.byref(params))
+
+
+def lbm_fused_plan(params, cus=256):
+    """Launch plan of the fused step for these parameters on a device with `cus` compute
+    units (host-only): a dict with the fields of lbm_fused_plan_t."""
+    out = lbm_fused_plan_t()
+    _check(library().lbm_fused_plan(ctypes.byref(params), int(cus), ctypes.byref(out)))
+    return {n: getattr(out, n) for n, _ in lbm_fused_plan_t._fields_}
 
 
 def _check_batch(status):

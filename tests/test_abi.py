@@ -132,3 +132,70 @@ def test_create_rejects_invalid_parameters_before_touching_the_device(changes, m
         lbm.lbm_create(_bad(**changes))
     assert ei.value.status == lbm.LBM_EINVAL
     assert message in str(ei.value), str(ei.value)
+
+
+def _plan_params(lbm, nx, ny, nz, storage=1, Q=19, cylinder=False):
+    p = lbm.lbm_params_default()
+    p.nx, p.ny, p.nz, p.storage, p.lattice = nx, ny, nz, storage, Q
+    if cylinder:
+        p.cylinder, p.cyl_y, p.cyl_z, p.cyl_r = 1, ny / 2.0, 10.0, 8.0
+    return p
+
+
+@pytest.mark.parametrize("shape,storage,Q,expect", [
+    # 256^3 D3Q19 FP32: prefetching 256x4 full rows, one round of 256 workgroups
+    ((256, 256, 256), 1, 19, dict(config=3, tile_x=256, tile_y=4, full_rows=1, prefetch=1, z_chunk=64,
+                                  xcd_order=1, hints=3, workgroups=256)),
+    # FP64: plain 256x2 full rows, 128-plane chunks, plain stores
+    ((256, 256, 256), 0, 19, dict(config=1, tile_y=2, prefetch=0, z_chunk=128, hints=0, workgroups=256)),
+    # FP16: as FP32 with nontemporal stores only
+    ((256, 256, 256), 2, 19, dict(config=3, prefetch=1, z_chunk=64, hints=1)),
+    # D3Q27 FP32: prefetching 256x2, plain stores; FP64 own-population prefetch; FP16 plain
+    ((256, 256, 256), 1, 27, dict(config=4, tile_y=2, prefetch=1, z_chunk=128, hints=0)),
+    ((256, 256, 256), 0, 27, dict(config=4, prefetch=1, z_chunk=128, hints=1)),
+    ((256, 256, 256), 2, 27, dict(config=1, prefetch=0, z_chunk=128, hints=1)),
+    # one GPU's z-slab of 256^3 cut eight ways: 8-plane chunks fill the CUs
+    ((256, 256, 32), 1, 19, dict(config=3, z_chunk=8, workgroups=256)),
+    # 384-wide impact box: prefetching 384x2, three rounds of 48-plane chunks
+    ((384, 384, 192), 1, 19, dict(config=8, tile_x=384, tile_y=2, prefetch=1, z_chunk=48,
+                                  hints=0, workgroups=768)),
+    # D3Q27 at 384 wide does not fit the prefetch buffers: plain 384x2
+    ((384, 256, 64), 1, 27, dict(config=7, prefetch=0)),
+    ((320, 256, 192), 1, 27, dict(config=5, tile_x=320, prefetch=0, z_chunk=96)),
+    # other widths: 64x8 tiles for 4-byte storage, 64x4 otherwise, 16-plane chunks
+    ((300, 300, 250), 1, 19, dict(config=10, tile_x=64, tile_y=8, full_rows=0, z_chunk=16, hints=0)),
+    ((300, 300, 250), 2, 27, dict(config=9, tile_x=64, tile_y=4, z_chunk=16)),
+    ((384, 384, 160), 0, 19, dict(config=9, full_rows=0)),
+])
+def test_fused_launch_plan(monkeypatch, shape, storage, Q, expect):
+    """The fused step's launch plan (tile shape, prefetch, z-chunks, hints, grid) for the
+    workloads the defaults were tuned on, computed on the host for 256 CUs."""
+    from paper_2306_16274_amd import lbm
+    for k in ("LBM_FUSED_CONFIG", "LBM_FUSED_ZC", "LBM_FUSED_HINTS", "LBM_FUSED_REMAP"):
+        monkeypatch.delenv(k, raising=False)
+    plan = lbm.lbm_fused_plan(_plan_params(lbm, *shape, storage=storage, Q=Q))
+    for k, v in expect.items():
+        assert plan[k] == v, (k, plan)
+
+
+def test_fused_launch_plan_overrides_and_errors(monkeypatch):
+    from paper_2306_16274_amd import lbm
+    p = _plan_params(lbm, 256, 256, 256)
+    monkeypatch.setenv("LBM_FUSED_ZC", "7")
+    monkeypatch.setenv("LBM_FUSED_CONFIG", "0")
+    plan = lbm.lbm_fused_plan(p)
+    assert plan["config"] == 0 and plan["tile_x"] == 32 and plan["z_chunk"] == 7
+    assert plan["workgroups"] == 8 * 32 * 37
+    monkeypatch.setenv("LBM_FUSED_CONFIG", "7")        # a 384-wide configuration on 256: ignored
+    assert lbm.lbm_fused_plan(p)["config"] == 3
+    monkeypatch.delenv("LBM_FUSED_CONFIG")
+    monkeypatch.delenv("LBM_FUSED_ZC")
+    # fewer CUs: fewer chunks per column of tiles
+    assert lbm.lbm_fused_plan(p, cus=128)["z_chunk"] == 128
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_fused_plan(p, cus=0)
+    bad = _plan_params(lbm, 256, 256, 256)
+    bad.lattice = 15
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.lbm_fused_plan(bad)
+    assert ei.value.status == lbm.LBM_EINVAL
