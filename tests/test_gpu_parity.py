@@ -113,6 +113,29 @@ def test_fp64_brute_force_tiny_box(L, Q, geometry, kernel):
         assert abs_err(mom["p"], po, fl) < 1e-13
 
 
+@KERNELS
+@pytest.mark.parametrize("Q", [19, 27])
+@pytest.mark.parametrize("shape,walls", [((1, 6, 5), ()), ((5, 1, 4), ("z_lo", "z_hi")),
+                                         ((4, 3, 1), ()), ((2, 2, 2), ())])
+def test_fp64_brute_force_degenerate_extents(L, Q, shape, walls, kernel):
+    """Extents of 1 and 2 nodes (a quasi-2D sheet, a single row between walls, a single
+    plane, the smallest cube): the periodic wrap then maps a node's neighbours onto itself
+    or its one partner, which the tiles (wider than the domain) must reproduce; 1 and 10
+    steps against the oracle."""
+    nx, ny, nz = shape
+    w = si.Workload("degenerate", Q, nx, ny, nz, sigma=0.1, kappa=0.3, G_ads=0.1, nu=0.05,
+                    T_over_Tc=0.6, walls=walls)
+    rho, u = si.random_fields(w.shape, seed=5, rho_lo=0.05, rho_hi=0.4)
+    P, solid, f0 = oracle_state_from_fields(w, rho, u)
+    f0 = f0 * si.random_factors(Q, w.shape, seed=5, amp=0.02)
+    for steps in (1, 10):
+        fo = olbm.run(f0, P, steps, solid)
+        g, mom = run_pair(L, w, f0, steps, step_kernel=kernel_code(L, kernel))
+        assert abs_err(g, fo) < 1e-13, steps
+        ro, _, _, _ = olbm.moments(fo, P, solid)
+        assert rel_err(mom["rho"], ro, ~solid) < 1e-12
+
+
 def _static32(Q=19):
     w = si.STATIC_32.with_(Q=Q)
     rv, rl = maxwell(w)
