@@ -396,8 +396,9 @@ def test_full_size_impact_384x384x192_sampled_windows(L):
     z = 191, CS at 0.55 T_c, R = 40 at z = 50 falling at 0.05, nu = 0.001, FP32 shifted
     storage) in its default launch configuration (prefetching 384x2 full-row tiles, 48-plane
     z-chunks): one GPU step from a read-back state against the oracle on windows at both
-    walls, the droplet's foot, interface and interior, the vapour and random places. G_ads = 0 (the config's 90 degree
-    wall is nominal: the wetting force enters through the same code path at any value)."""
+    walls, the droplet's foot, interface and interior, the vapour and random places.
+    G_ads = 0 (the config's 90 degree wall is nominal: the wetting force enters through the
+    same code path at any value)."""
     w = si.IMPACT_384
     rv, rl = maxwell(w)
     cx, cy, cz = w.droplet_centre()
@@ -416,6 +417,34 @@ def test_full_size_impact_384x384x192_sampled_windows(L):
     er, ef = _sampled_window_errors(w, f3, f4, centres, solid)
     print(f"384x384x192 fp32: worst relative rho {er:.2e}, worst |df| {ef:.2e}")
     assert er < 1e-6
+
+
+def test_largest_fused_buffer_sampled_windows(L):
+    """The largest lattice of its width the fused step takes: 384 x 384 x 368 D3Q19 FP32
+    (population buffer 4.12 GB, just under the 4 GiB of the kernels' 32-bit byte offsets),
+    periodic, a droplet of R = 60 with interface noise, in its default launch configuration
+    (prefetching 384x2 tiles). One GPU step from a read-back state against the oracle on
+    windows in the last planes and the last population planes' reach (the highest offsets),
+    the first planes, the interface and random places; and 384 x 384 x 384 is rejected."""
+    w = si.LAPLACE_256.with_(nx=384, ny=384, nz=368, R=60.0, centre=(192, 192, 184))
+    assert 19 * 384 * 384 * 368 * 4 < 2 ** 32 <= 19 * 384 ** 3 * 4
+    rv, rl = maxwell(w)
+    with L.Lattice(gpu_params(w, "fp32", rho_ref=rv)) as lat:
+        lat.init_droplet(*w.droplet_centre(), w.R, w.W, rl, rv, 0.0, 0.0, 0.0, w.noise, w.seed)
+        lat.step(2)
+        f3 = lat.get_populations()
+        lat.step(1)
+        f4 = lat.get_populations()
+    rng = np.random.default_rng(368)
+    centres = [(367, 383, 383), (366, 200, 10), (0, 0, 0), (184, 192, 192 + 60), (184, 192, 192),
+               (124, 192, 192)]
+    centres += [(int(rng.integers(0, 368)), int(rng.integers(0, 384)), int(rng.integers(0, 384)))
+                for _ in range(4)]
+    er, ef = _sampled_window_errors(w, f3, f4, centres)
+    print(f"384x384x368 fp32: worst relative rho {er:.2e}, worst |df| {ef:.2e}")
+    assert er < 1e-6
+    with pytest.raises(L.LbmError):
+        L.Lattice(gpu_params(w.with_(nz=384), "fp32", rho_ref=rv))
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp64", "fp16"])
