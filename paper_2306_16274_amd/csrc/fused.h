@@ -415,18 +415,25 @@ __device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F);
 // Asynchronous load of one element per lane from global memory into LDS (the lane's element
 // lands at dst + 4 * lane); AUX selects the cache policy (0 default, 2 nontemporal).
 // (The builtin takes its size and policy as literal constants, hence one specialization each.)
-template <int SIZE, int AUX> __device__ __forceinline__ void lds_dma(const char* src, void* dst);
-template <> __device__ __forceinline__ void lds_dma<4, 0>(const char* src, void* dst) {
-    __builtin_amdgcn_global_load_lds(src, LBM_LDS_PTR(dst), 4, 0, 0);
+// The LDS destination is a wave-uniform byte address (it goes to M0): callers form it with
+// scalar arithmetic from lds_addr(), so no per-load readfirstlane is needed.
+#define LBM_LDS_AT(a) ((__attribute__((address_space(3))) void*)(a))
+template <int SIZE, int AUX> __device__ __forceinline__ void lds_dma(const char* src, uint32_t dst);
+template <> __device__ __forceinline__ void lds_dma<4, 0>(const char* src, uint32_t dst) {
+    __builtin_amdgcn_global_load_lds(src, LBM_LDS_AT(dst), 4, 0, 0);
 }
-template <> __device__ __forceinline__ void lds_dma<4, 2>(const char* src, void* dst) {
-    __builtin_amdgcn_global_load_lds(src, LBM_LDS_PTR(dst), 4, 0, 2);
+template <> __device__ __forceinline__ void lds_dma<4, 2>(const char* src, uint32_t dst) {
+    __builtin_amdgcn_global_load_lds(src, LBM_LDS_AT(dst), 4, 0, 2);
 }
-template <> __device__ __forceinline__ void lds_dma<2, 0>(const char* src, void* dst) {
-    __builtin_amdgcn_global_load_lds(src, LBM_LDS_PTR(dst), 2, 0, 0);
+template <> __device__ __forceinline__ void lds_dma<2, 0>(const char* src, uint32_t dst) {
+    __builtin_amdgcn_global_load_lds(src, LBM_LDS_AT(dst), 2, 0, 0);
 }
-template <> __device__ __forceinline__ void lds_dma<2, 2>(const char* src, void* dst) {
-    __builtin_amdgcn_global_load_lds(src, LBM_LDS_PTR(dst), 2, 0, 2);
+template <> __device__ __forceinline__ void lds_dma<2, 2>(const char* src, uint32_t dst) {
+    __builtin_amdgcn_global_load_lds(src, LBM_LDS_AT(dst), 2, 0, 2);
+}
+// Wave-uniform LDS byte address of a shared object (as a scalar).
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+    return __builtin_amdgcn_readfirstlane((uint32_t)(size_t)LBM_LDS_PTR(p));
 }
 
 // Prefetch slots: the LDS DMA writes each lane's element into a dword of its own (a 2-byte
@@ -460,13 +467,16 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
     // the halo buffer holds H cells; the DMA of the last, partly used wavefront writes only
     // its active lanes
     __shared__ S pf_halo[Q][H];
+    // this wavefront's slots of population 0 in the two buffers (scalars)
+    const uint32_t own_lds = lds_addr(&pf_own[0][(threadIdx.x >> 6) * 64]);
+    const uint32_t halo_lds = lds_addr(&pf_halo[0][(threadIdx.x >> 6) * 64]);
 
     const int ix = t % ntx; t /= ntx;
     const int iy = t % nty;
     const int iz = t / nty;
     const int x0 = ix * TX, y0 = iy * TY, z0 = iz * zc;
     const int z1 = min(z0 + zc, g.nz);
-    const int tid = threadIdx.x, wave = tid >> 6;
+    const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
     const int x = x0 + lx, y = y0 + ly;
     const bool active = x < g.nx && y < g.ny;
@@ -556,7 +566,7 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
                 pull_source<Q, GEOM>(i, oxy, zo, lk, wb, e, pop);
                 lds_dma<(int)sizeof(T), 2>(
                     reinterpret_cast<const char*>(fin) + ((unsigned)e * (unsigned)sizeof(T) + (unsigned)pop * pst),
-                    &pf_own[i][wave * 64]);
+                    own_lds + (uint32_t)(i * NT * sizeof(S)));
             }
         } else {
 #pragma unroll
@@ -565,7 +575,7 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
                 pull_source<Q, GEOM>(i, oxy, zo, lk, wb, e, pop);
                 lds_dma<(int)sizeof(T), 0>(
                     reinterpret_cast<const char*>(fin) + ((unsigned)e * (unsigned)sizeof(T) + (unsigned)pop * pst),
-                    &pf_own[i][wave * 64]);
+                    own_lds + (uint32_t)(i * NT * sizeof(S)));
             }
         }
     };
@@ -581,7 +591,7 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
             pull_source<Q, GEOM>(i, hxy, zo, lk, hb, e, pop);
             lds_dma<(int)sizeof(T), 0>(
                 reinterpret_cast<const char*>(fin) + ((unsigned)e * (unsigned)sizeof(T) + (unsigned)pop * pst),
-                &pf_halo[i][wave * 64]);
+                halo_lds + (uint32_t)(i * H * sizeof(S)));
         }
     };
     // plane zp from the LDS buffers: psi of the halo node; own populations into v and psi
@@ -683,12 +693,14 @@ __device__ __forceinline__ void fused_tile_pf64(const double* __restrict__ fin,
     __shared__ R ring[4][TY + 2][TX];
     __shared__ uint32_t pf_lo[Q][NT];
     __shared__ uint32_t pf_hi[Q][NT];
+    const uint32_t lo_lds = lds_addr(&pf_lo[0][(threadIdx.x >> 6) * 64]);
+    const uint32_t hi_lds = lds_addr(&pf_hi[0][(threadIdx.x >> 6) * 64]);
 
     const int iy = t % nty;
     const int iz = t / nty;
     const int y0 = iy * TY, z0 = iz * zc;
     const int z1 = min(z0 + zc, g.nz);
-    const int tid = threadIdx.x, wave = tid >> 6;
+    const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
     const int x = lx, y = y0 + ly;
     const bool active = y < g.ny;
@@ -757,8 +769,8 @@ __device__ __forceinline__ void fused_tile_pf64(const double* __restrict__ fin,
             int e, pop;
             pull_source<Q, GEOM>(i, oxy, zo, lk, wb, e, pop);
             const char* src = reinterpret_cast<const char*>(fin) + ((unsigned)e * 8u + (unsigned)pop * pst);
-            lds_dma<4, 0>(src, &pf_lo[i][wave * 64]);
-            lds_dma<4, 0>(src + 4, &pf_hi[i][wave * 64]);
+            lds_dma<4, 0>(src, lo_lds + (uint32_t)(i * NT * 4));
+            lds_dma<4, 0>(src + 4, hi_lds + (uint32_t)(i * NT * 4));
         }
     };
     auto take_own = [&](int zp, int slot, R* v) {
