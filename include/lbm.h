@@ -219,8 +219,9 @@ lbm_status lbm_fused_plan(const lbm_params* p, int32_t cus, lbm_fused_plan_t* ou
  * steps_per_launch consecutive launches are captured once into a HIP graph. Each member
  * takes exactly the time step of lbm_step (bitwise the same populations: the per-node
  * arithmetic is shared). The batched step runs 64x4 tiles through 16-plane z-chunks, with
- * nontemporal stores when every member's rows are whole 128-byte lines; LBM_BATCH_TILE,
- * LBM_BATCH_ZC, LBM_BATCH_PF and LBM_BATCH_NT override this for tuning.
+ * nontemporal stores when every member's rows are whole 128-byte lines, its workgroups
+ * mapped to XCDs in contiguous ranges; LBM_BATCH_TILE, LBM_BATCH_ZC, LBM_BATCH_PF,
+ * LBM_BATCH_NT and LBM_BATCH_REMAP override this for tuning.
  * The batch borrows the contexts (they must outlive it and must not be stepped on their
  * own while the batch runs); it orders its work after, and each member's later work
  * after, the batch's graph launches through events.

@@ -870,12 +870,13 @@ struct DomainDesc {
     int ntx, nty, zc, block0;
 };
 
-// Many independent lattices advanced by one launch: workgroup b belongs to the last
-// domain whose block0 <= b (binary search over the table, uniform per workgroup).
+// Many independent lattices advanced by one launch: workgroup b (after the XCD-contiguous
+// remap when remap != 0) belongs to the last domain whose block0 <= b (binary search over
+// the table, uniform per workgroup).
 template <int Q, typename T, int GEOM, int TX, int TY, bool NTS>
 __global__ __launch_bounds__(TX * TY) void k_step_fused_batch(const DomainDesc<T>* __restrict__ d,
-                                                             int ndom) {
-    const int b = blockIdx.x;
+                                                             int ndom, int remap) {
+    const int b = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     int lo = 0, hi = ndom - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -889,8 +890,8 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_batch(const DomainDesc<T
 // Batched step with prefetching tiles (4-byte storage): as k_step_fused_batch.
 template <int Q, typename T, int GEOM, int TX, int TY, bool NTS>
 __global__ __launch_bounds__(TX * TY) void k_step_fused_batch_pf(const DomainDesc<T>* __restrict__ d,
-                                                                int ndom) {
-    const int b = blockIdx.x;
+                                                                int ndom, int remap) {
+    const int b = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     int lo = 0, hi = ndom - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;

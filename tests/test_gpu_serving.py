@@ -36,16 +36,20 @@ def _make(L, w, storage):
     return lat
 
 
-@pytest.mark.parametrize("variant", ["plain", "plain_nt", "prefetch", "prefetch_nt", "tiles32x8"])
+@pytest.mark.parametrize("variant", ["plain", "plain_nt", "prefetch", "prefetch_nt", "tiles32x8",
+                                     "dispatch_order"])
 @pytest.mark.parametrize("storage", ["fp32", "fp64"])
 def test_batch_equals_individual_steps(L, monkeypatch, storage, variant):
-    """Batched launches (default plain 64x4 tiles, prefetching tiles, 32x8 tiles; plain
-    stores, the default for these unaligned rows, or nontemporal ones) give each member
-    exactly the populations of its own single-lattice steps."""
+    """Batched launches (default plain 64x4 tiles in XCD order, prefetching tiles, 32x8
+    tiles, dispatch order; plain stores, the default for these unaligned rows, or
+    nontemporal ones) give each member exactly the populations of its own single-lattice
+    steps."""
     if variant.startswith("prefetch"):
         monkeypatch.setenv("LBM_BATCH_PF", "1")
     if variant.endswith("_nt"):
         monkeypatch.setenv("LBM_BATCH_NT", "1")
+    if variant == "dispatch_order":
+        monkeypatch.setenv("LBM_BATCH_REMAP", "0")
     if variant == "tiles32x8":
         monkeypatch.setenv("LBM_BATCH_TILE", "1")
     ws = _members()
