@@ -99,7 +99,7 @@ lbm_status lbm_params_default(lbm_params* p);
    EOS, boundary condition or step kernel, sizes < 1 or beyond the launch grid, G >= 0,
    non-positive EOS constants, rates outside (0,2), nu <= 0, non-finite parameters, a
    cylinder radius <= 0, an EOS without a two-phase region, a geometry without fluid
-   nodes, a fused step on a population buffer of 4 GiB or more. The populations are
+   nodes, more than 2^31 - 1 nodes. The populations are
    undefined until one of the lbm_init_* / lbm_set_populations calls.                  */
 lbm_status lbm_create(const lbm_params* p, lbm_ctx** out);
 
@@ -137,7 +137,8 @@ lbm_status lbm_get_populations(lbm_ctx* c, double* f);
    result of the previous health check is read. nsteps >= 0.
    The launch configuration of the fused step (tile shape: full rows for nx = 256, 320 or
    384, else 64x8 or 64x4 tiles; z-chunk length; nontemporal hints) is chosen from the
-   domain width, the storage type and the lattice. For tuning, the environment variables
+   domain width, the storage type and the lattice; a population buffer of 4 GiB or more
+   takes 64x8 (4-byte storage) or 64x4 tiles with 64-bit offsets and plain stores. For tuning, the environment variables
    LBM_FUSED_CONFIG, LBM_FUSED_ZC, LBM_FUSED_REMAP and LBM_FUSED_HINTS override it; every
    configuration gives bitwise the same populations.                                   */
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps);
@@ -208,6 +209,7 @@ typedef struct {
     int32_t z_chunk;      /* planes marched by one workgroup (LBM_FUSED_ZC)                 */
     int32_t xcd_order;    /* 1: tiles mapped to XCDs in contiguous ranges (LBM_FUSED_REMAP) */
     int32_t hints;        /* bit 0: nontemporal stores; bit 1: nontemporal interior loads  */
+    int32_t addr64;       /* 1: 64-bit byte offsets (population buffer of 4 GiB or more)    */
     int64_t workgroups;   /* workgroups of one time step                                    */
 } lbm_fused_plan_t;
 lbm_status lbm_fused_plan(const lbm_params* p, int32_t cus, lbm_fused_plan_t* out);

@@ -46,11 +46,13 @@ struct lbm_ctx {
     Phys<float> pf{};
     int fused_cfg = 0;             // index into kFusedCfgs
     int cus = 256;                 // compute units of the device
+    bool addr64 = false;           // population buffer of 4 GiB or more: 64-bit offsets
     std::string err;
 };
 
 static thread_local std::string g_create_error;   // per calling thread
 static int default_fused_cfg(const lbm_ctx* c);
+static bool needs_addr64(const lbm_params& p);
 
 static lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
     char buf[512];
@@ -277,10 +279,6 @@ static lbm_status validate(const lbm_params& p) {
     if (p.reduce_every < 0) return fail(nullptr, LBM_EINVAL, "reduce_every must be >= 0");
     if (p.step_kernel != LBM_STEP_FUSED && p.step_kernel != LBM_STEP_TWO_PASS)
         return fail(nullptr, LBM_EINVAL, "unknown step_kernel");
-    if (p.step_kernel == LBM_STEP_FUSED &&
-        (double)(p.lattice == 27 ? 27 : 19) * (double)plane_stride(N) * (double)storage_bytes(p.storage) >= 4294967296.0)
-        return fail(nullptr, LBM_EINVAL,
-                    "population buffer of 4 GiB or more: use step_kernel = LBM_STEP_TWO_PASS");
     return LBM_OK;
 }
 
@@ -390,6 +388,7 @@ extern "C" lbm_status lbm_create(const lbm_params* pp, lbm_ctx** out) {
     c->elem = storage_bytes(pp->storage);
     c->pd = make_phys<double>(*pp);
     c->pf = make_phys<float>(*pp);
+    c->addr64 = pp->step_kernel == LBM_STEP_FUSED && needs_addr64(*pp);
     c->fused_cfg = default_fused_cfg(c);
     auto bail = [&](lbm_status s) { g_create_error = c->err; free_all(c); delete c; return s; };
 #define CHK(call) do { hipError_t e_ = (call); if (e_ != hipSuccess) {                     \
@@ -498,19 +497,31 @@ static const char* const kFusedNames[] = {"k_step_fused"};
 // Tile configurations of the fused kernel. 256 x 2 full rows: the x-shifted pulls of a
 // row stay inside one workgroup and the halo is two rows; 64x8 or 64x4 tiles for other widths.
 
+// Population buffers of 4 GiB or more take 64-bit byte offsets, which only the plain 64x4
+// and 64x8 tiles are instantiated with (configurations 9 and 10).
+static bool needs_addr64(const lbm_params& p) {
+    const long long N = (long long)p.nx * p.ny * p.nz;
+    return (double)(p.lattice == 27 ? 27 : 19) * (double)plane_stride(N) *
+               (double)storage_bytes(p.storage) >= 4294967296.0;
+}
+
 // Launch configuration of the fused step for a lattice of width nx, element size elem and
 // lattice Q: the default of fused.h unless LBM_FUSED_CONFIG names a valid one (a full-row
-// configuration needs nx equal to its width; FP64 has no 320/384-wide instantiations).
-static int fused_cfg_for(int nx, int elem, int Q) {
+// configuration needs nx equal to its width; FP64 has no 320/384-wide instantiations; with
+// 64-bit offsets only configurations 9 and 10 exist).
+static int fused_cfg_for(int nx, int elem, int Q, bool addr64) {
     if (const char* e = getenv("LBM_FUSED_CONFIG")) {      // tuning override
         const int v = atoi(e);
         if (v >= 0 && v < kNumFusedCfgs && (!kFusedCfgs[v].fullx || nx == kFusedCfgs[v].tx) &&
-            !(elem == 8 && kFusedCfgs[v].tx > 256))
+            !(elem == 8 && kFusedCfgs[v].tx > 256) && (!addr64 || v == 9 || v == 10))
             return v;
     }
+    if (addr64) return elem == 4 ? 10 : 9;
     return default_fused_cfg_index(nx, elem, Q);
 }
-static int default_fused_cfg(const lbm_ctx* c) { return fused_cfg_for(c->p.nx, (int)c->elem, c->Q); }
+static int default_fused_cfg(const lbm_ctx* c) {
+    return fused_cfg_for(c->p.nx, (int)c->elem, c->Q, c->addr64);
+}
 
 // Whether a configuration's prefetching tile fits in LDS for this lattice and element size
 // (the launch falls back to the plain tile of the same shape otherwise).
@@ -550,7 +561,8 @@ extern "C" lbm_status lbm_fused_plan(const lbm_params* p, int32_t cus, lbm_fused
     const lbm_status st = validate(*p);
     if (st != LBM_OK) return st;
     const int elem = (int)storage_bytes(p->storage), Q = p->lattice;
-    const int cfg = fused_cfg_for(p->nx, elem, Q);
+    const bool addr64 = needs_addr64(*p);
+    const int cfg = fused_cfg_for(p->nx, elem, Q, addr64);
     const FusedCfg& f = kFusedCfgs[cfg];
     const FusedPlan pl = fused_plan(*p, elem, cfg, cus);
     out->config = cfg;
@@ -560,7 +572,8 @@ extern "C" lbm_status lbm_fused_plan(const lbm_params* p, int32_t cus, lbm_fused
     out->prefetch = fused_prefetch_fits(f, Q, elem) ? 1 : 0;
     out->z_chunk = pl.zc;
     out->xcd_order = pl.remap;
-    out->hints = pl.hints;
+    out->hints = addr64 ? (pl.hints & ~kHintNtStore) : pl.hints;
+    out->addr64 = addr64 ? 1 : 0;
     out->workgroups = pl.workgroups;
     return LBM_OK;
 }
@@ -586,7 +599,7 @@ static void with_geom_nts(const lbm_ctx* c, int hints, F&& f) {
     }
 }
 
-template <int Q, typename T, int TX, int TY, bool FULLX>
+template <int Q, typename T, int TX, int TY, bool FULLX, bool WIDE = false>
 static void launch_fused_cfg(lbm_ctx* c, const void* fin, void* fout) {
     using R = typename Arith<T>::type;
     const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
@@ -597,12 +610,13 @@ static void launch_fused_cfg(lbm_ctx* c, const void* fin, void* fout) {
     fused_chunking(c, zc, remap, hints);
     const int nchunks = (c->p.nz + zc - 1) / zc;
     const dim3 grid((unsigned)(tiles * nchunks)), block(TX * TY);
-    // the kernel addresses populations with 32-bit byte offsets (checked at create)
-    with_geom_nts(c, hints, [&](auto geom, auto nts) {
-        hipLaunchKernelGGL((k_step_fused<Q, T, decltype(geom)::value, TX, TY, FULLX,
-                                         decltype(nts)::value>),
-                           grid, block, 0, c->stream, (const T*)fin, (T*)fout, c->links,
-                           grid_of(c), P, ntx, nty, zc, remap, hints);
+    // 64-bit offsets are instantiated with plain stores only
+    with_geom_nts(c, WIDE ? (hints & ~kHintNtStore) : hints, [&](auto geom, auto nts) {
+        if constexpr (!WIDE || !decltype(nts)::value)
+            hipLaunchKernelGGL((k_step_fused<Q, T, decltype(geom)::value, TX, TY, FULLX,
+                                             decltype(nts)::value, WIDE>),
+                               grid, block, 0, c->stream, (const T*)fin, (T*)fout, c->links,
+                               grid_of(c), P, ntx, nty, zc, remap, hints);
     });
 }
 
@@ -659,6 +673,11 @@ static void launch_fused_wide(lbm_ctx* c, const void* fin, void* fout) {
 
 template <int Q, typename T>
 static void launch_fused(lbm_ctx* c, const void* fin, void* fout) {
+    if (c->addr64) {                       // population buffer of 4 GiB or more
+        if (c->fused_cfg == 9) launch_fused_cfg<Q, T, 64, 4, false, true>(c, fin, fout);
+        else launch_fused_cfg<Q, T, 64, 8, false, true>(c, fin, fout);
+        return;
+    }
     switch (c->fused_cfg) {
     case 1: launch_fused_cfg<Q, T, 256, 2, true>(c, fin, fout); break;
     case 2: launch_fused_cfg<Q, T, 256, 4, true>(c, fin, fout); break;

@@ -19,9 +19,9 @@
 //     share an L2 and the halo re-reads stay on chip;
 //   * with a cylinder, solidity comes from one 32-bit link word per node (bit 0: the node,
 //     bit i: its neighbour x - e_i), not from a byte load per population;
-//   * addresses are 32-bit byte offsets from the buffer base (the host checks that the
-//     population buffer is below 4 GiB), with the in-plane offsets of the 3x3 column
-//     neighbourhood computed once per thread.
+//   * addresses are 32-bit byte offsets from the buffer base below 4 GiB of populations,
+//     64-bit offsets (plain 64x4 / 64x8 tiles only) from there on, with the in-plane
+//     offsets of the 3x3 column neighbourhood computed once per thread.
 //
 // Every LDS cell stands for a node with periodically wrapped coordinates, so tiles that
 // cross the domain edge (or are wider than the domain) need no special case: threads
@@ -150,17 +150,22 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return xcd * q + (xcd < r ? xcd : r) + k;
 }
 
-template <typename T>
-__device__ __forceinline__ T ld_off(const T* __restrict__ base, unsigned byte_off) {
+// Byte offsets from the buffer base: 32-bit (buffers below 4 GiB, the scalar base plus a
+// 32-bit vector offset) or 64-bit (larger buffers, the plain small-tile kernel only).
+template <bool WIDE> struct OffSel { using type = unsigned; };
+template <> struct OffSel<true> { using type = size_t; };
+
+template <typename T, typename Off>
+__device__ __forceinline__ T ld_off(const T* __restrict__ base, Off byte_off) {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
 }
-template <typename T>
-__device__ __forceinline__ void st_off(T* __restrict__ base, unsigned byte_off, T v) {
+template <typename T, typename Off>
+__device__ __forceinline__ void st_off(T* __restrict__ base, Off byte_off, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 // Streaming store (nontemporal hint).
-template <typename T>
-__device__ __forceinline__ void st_off_nt(T* __restrict__ base, unsigned byte_off, T v) {
+template <typename T, typename Off>
+__device__ __forceinline__ void st_off_nt(T* __restrict__ base, Off byte_off, T v) {
     __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off));
 }
 
@@ -216,16 +221,16 @@ __device__ __forceinline__ bool node_solid(const uint32_t* __restrict__ links, i
 }
 
 // Issue the Q loads of a column's node (values land in v[]).
-template <int Q, typename T, typename R, int GEOM>
+template <int Q, typename T, typename R, int GEOM, typename Off = unsigned>
 __device__ __forceinline__ void pull_loads(const T* __restrict__ f, const uint32_t* __restrict__ links,
                                            const int* xy, const int* zo, const WallBits& wb,
-                                           unsigned pst, R* v) {
+                                           Off pst, R* v) {
     const unsigned lk = link_word<GEOM>(links, xy[4] + zo[1]);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         int e, pop;
         pull_source<Q, GEOM>(i, xy, zo, lk, wb, e, pop);
-        v[i] = static_cast<R>(ld_off(f, (unsigned)e * (unsigned)sizeof(T) + (unsigned)pop * pst));
+        v[i] = static_cast<R>(ld_off(f, (Off)e * (Off)sizeof(T) + (Off)pop * pst));
     }
 }
 
@@ -242,7 +247,7 @@ __device__ __forceinline__ R sum_q(const R* v) {
 // One tile (workgroup) of the fused step: tile index t of a domain with ntx x nty tiles
 // per plane and z-chunks of zc planes. Shared by the single-domain kernel and the
 // multi-domain (batched) kernel.
-template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX, bool NTS>
+template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX, bool NTS, bool WIDE = false>
 __device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restrict__ fout,
                                            const uint32_t* __restrict__ links, const Grid& g,
                                            const Phys<typename Arith<T>::type>& P,
@@ -265,7 +270,8 @@ __device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restr
     const bool active = x < g.nx && y < g.ny;
     auto wrapc = [](int c, int n) { c %= n; return c < 0 ? c + n : c; };
     const int nxy = g.nx * g.ny;
-    const unsigned pst = (unsigned)g.stride * (unsigned)sizeof(T);   // plane stride, bytes
+    using Off = typename OffSel<WIDE>::type;
+    const Off pst = (Off)g.stride * (Off)sizeof(T);   // plane stride, bytes
 
     // halo cell of this thread (if any), as tile coordinates (hx, hy)
     int hx = 0, hy = 0;
@@ -314,7 +320,7 @@ __device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restr
         if (node_solid<GEOM>(links, hxy[4] + zo[1], wb)) hv = R(-1);
         else {
             R v[Q];
-            pull_loads<Q, T, R, GEOM>(fin, links, hxy, zo, wb, pst, v);
+            pull_loads<Q, T, R, GEOM, Off>(fin, links, hxy, zo, wb, pst, v);
             hv = psi_of(sum_q<Q, R>(v));
         }
         ring[slot][hy + 1][hx + OX] = hv;
@@ -325,7 +331,7 @@ __device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restr
         zoffs(zp, zo);
         const WallBits wb{wo.wx, wo.wy, zbits(zp)};
         const bool s = node_solid<GEOM>(links, oxy[4] + zo[1], wb);
-        pull_loads<Q, T, R, GEOM>(fin, links, oxy, zo, wb, pst, v);
+        pull_loads<Q, T, R, GEOM, Off>(fin, links, oxy, zo, wb, pst, v);
         ring[slot][ly + 1][lx + OX] = s ? R(-1) : psi_of(sum_q<Q, R>(v));
     };
     // LDS column of tile column lx + dx
@@ -346,13 +352,13 @@ __device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restr
             }
             const NodeForce<R> nf = node_force<Q, R>(psi0, pn, P);
             collide<Q, R>(c, nf, P);
-            const unsigned nb = (unsigned)(oxy[4] + z * nxy) * (unsigned)sizeof(T);
+            const Off nb = (Off)(oxy[4] + z * nxy) * (Off)sizeof(T);
             if constexpr (NTS) {
 #pragma unroll
-                for (int i = 0; i < Q; ++i) st_off_nt(fout, nb + (unsigned)i * pst, static_cast<T>(c[i]));
+                for (int i = 0; i < Q; ++i) st_off_nt(fout, nb + (Off)i * pst, static_cast<T>(c[i]));
             } else {
 #pragma unroll
-                for (int i = 0; i < Q; ++i) st_off(fout, nb + (unsigned)i * pst, static_cast<T>(c[i]));
+                for (int i = 0; i < Q; ++i) st_off(fout, nb + (Off)i * pst, static_cast<T>(c[i]));
             }
         }
     };
@@ -847,7 +853,7 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_pf(const T* __restrict__
 
 // Single domain. remap != 0: map workgroups to tiles so that each XCD gets a contiguous
 // tile range (workgroup b runs on XCD b mod 8).
-template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX, bool NTS>
+template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX, bool NTS, bool WIDE = false>
 __global__ __launch_bounds__(TX * TY) void k_step_fused(const T* __restrict__ fin,
                                                        T* __restrict__ fout,
                                                        const uint32_t* __restrict__ links,
@@ -855,7 +861,7 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(const T* __restrict__ fi
                                                        int ntx, int nty, int zc, int remap,
                                                        int hints) {
     const int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    fused_tile<Q, T, GEOM, TX, TY, FULLX, NTS>(fin, fout, links, g, P, t, ntx, nty, zc, hints);
+    fused_tile<Q, T, GEOM, TX, TY, FULLX, NTS, WIDE>(fin, fout, links, g, P, t, ntx, nty, zc, hints);
 }
 
 // One domain of a batched step: its buffers, geometry, physics and the first workgroup

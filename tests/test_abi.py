@@ -121,7 +121,6 @@ def _bad(**changes):
     (dict(bc=3), "boundary"),
     (dict(reduce_every=-1), "reduce_every"),
     (dict(step_kernel=9), "step_kernel"),
-    (dict(lattice=27, storage=0, nx=512, ny=512, nz=512), "4 GiB"),
     (dict(T_over_Tc=1.2), "two-phase"),
 ])
 def test_create_rejects_invalid_parameters_before_touching_the_device(changes, message):
@@ -165,7 +164,11 @@ def _plan_params(lbm, nx, ny, nz, storage=1, Q=19, cylinder=False):
     # other widths: 64x8 tiles for 4-byte storage, 64x4 otherwise, 16-plane chunks
     ((300, 300, 250), 1, 19, dict(config=10, tile_x=64, tile_y=8, full_rows=0, z_chunk=16, hints=0)),
     ((300, 300, 250), 2, 27, dict(config=9, tile_x=64, tile_y=4, z_chunk=16)),
-    ((384, 384, 160), 0, 19, dict(config=9, full_rows=0)),
+    ((384, 384, 160), 0, 19, dict(config=9, full_rows=0, addr64=0)),
+    # population buffers of 4 GiB or more: 64x8 / 64x4 tiles with 64-bit offsets, plain stores
+    ((384, 384, 384), 1, 19, dict(config=10, full_rows=0, addr64=1, hints=0)),
+    ((512, 512, 512), 0, 27, dict(config=9, addr64=1, hints=0)),
+    ((384, 384, 368), 1, 19, dict(config=8, addr64=0)),
 ])
 def test_fused_launch_plan(monkeypatch, shape, storage, Q, expect):
     """The fused step's launch plan (tile shape, prefetch, z-chunks, hints, grid) for the

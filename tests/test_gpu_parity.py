@@ -420,12 +420,12 @@ def test_full_size_impact_384x384x192_sampled_windows(L):
 
 
 def test_largest_fused_buffer_sampled_windows(L):
-    """The largest lattice of its width the fused step takes: 384 x 384 x 368 D3Q19 FP32
-    (population buffer 4.12 GB, just under the 4 GiB of the kernels' 32-bit byte offsets),
+    """The largest lattice of its width on the 32-bit offsets: 384 x 384 x 368 D3Q19 FP32
+    (population buffer 4.12 GB, just under 4 GiB),
     periodic, a droplet of R = 60 with interface noise, in its default launch configuration
     (prefetching 384x2 tiles). One GPU step from a read-back state against the oracle on
     windows in the last planes and the last population planes' reach (the highest offsets),
-    the first planes, the interface and random places; and 384 x 384 x 384 is rejected."""
+    the first planes, the interface and random places."""
     w = si.LAPLACE_256.with_(nx=384, ny=384, nz=368, R=60.0, centre=(192, 192, 184))
     assert 19 * 384 * 384 * 368 * 4 < 2 ** 32 <= 19 * 384 ** 3 * 4
     rv, rl = maxwell(w)
@@ -443,8 +443,32 @@ def test_largest_fused_buffer_sampled_windows(L):
     er, ef = _sampled_window_errors(w, f3, f4, centres)
     print(f"384x384x368 fp32: worst relative rho {er:.2e}, worst |df| {ef:.2e}")
     assert er < 1e-6
-    with pytest.raises(L.LbmError):
-        L.Lattice(gpu_params(w.with_(nz=384), "fp32", rho_ref=rv))
+
+
+def test_fused_step_beyond_4gib_sampled_windows(L):
+    """A population buffer beyond 4 GiB (384^3 D3Q19 FP32, 4.30 GB): the fused step runs
+    64x8 tiles with 64-bit byte offsets. One GPU step from a read-back state against the
+    oracle on windows at the highest offsets (last planes, last rows), the first node, the
+    interface and random places; the launch plan reports the 64-bit path."""
+    w = si.LAPLACE_256.with_(nx=384, ny=384, nz=384, R=60.0, centre=(192, 192, 192))
+    assert 19 * 384 ** 3 * 4 >= 2 ** 32
+    rv, rl = maxwell(w)
+    p = gpu_params(w, "fp32", rho_ref=rv)
+    plan = L.lbm_fused_plan(p)
+    assert plan["addr64"] == 1 and plan["config"] == 10
+    with L.Lattice(p) as lat:
+        lat.init_droplet(*w.droplet_centre(), w.R, w.W, rl, rv, 0.0, 0.0, 0.0, w.noise, w.seed)
+        lat.step(2)
+        f3 = lat.get_populations()
+        lat.step(1)
+        f4 = lat.get_populations()
+    rng = np.random.default_rng(384)
+    centres = [(383, 383, 383), (382, 5, 200), (0, 0, 0), (192, 192, 252), (192, 192, 192)]
+    centres += [(int(rng.integers(0, 384)), int(rng.integers(0, 384)), int(rng.integers(0, 384)))
+                for _ in range(4)]
+    er, ef = _sampled_window_errors(w, f3, f4, centres)
+    print(f"384^3 fp32 (64-bit offsets): worst relative rho {er:.2e}, worst |df| {ef:.2e}")
+    assert er < 1e-6
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp64", "fp16"])
