@@ -230,7 +230,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "lattice": "D3Q19", "nodes": w.nodes,
                    "step_kernel": args.step_kernel,
-                   "eos": "carnahan-starling", "T_over_Tc": w.T_over_Tc,
+                   "eos": "carnahan-starling", "T_over_Tc": w.T_over_Tc, "rates": w.rates,
                    "storage": "fp32 shifted", "rho_ref": r32["rho_ref"],
                    "droplet_R": w.R, "noise": w.noise},
         "fp64": {"value": round(r64["mlups"], 1), "unit": "MLUPS",

@@ -60,10 +60,13 @@ class Workload:
 STATIC_32 = Workload("static-droplet-32^3-d3q19", 19, 32, 32, 32, T_over_Tc=0.7,
                      rates="unit", R=8.0, W=5.0, steps=200)
 
-# Static droplet for the Laplace law, 256^3 periodic D3Q19, CS EOS at 0.5 T_c, paper
-# rates, +-1 % density noise in the interface band. The headline throughput workload.
+# Static droplet for the Laplace law, 256^3 periodic D3Q19, CS EOS at 0.5 T_c, +-1 % density
+# noise in the interface band. The headline throughput workload. Non-viscous rates 1: with
+# the paper's rate set (bulk 0.6, others 1.2) droplets of R >= 30 at this temperature blow up
+# after 1100-1500 steps (the liquid density climbs to the psi^2 = 0 bound near 0.59), with
+# rates 1 they run the 5000 steps.
 LAPLACE_256 = Workload("laplace-droplet-256^3-d3q19", 19, 256, 256, 256, T_over_Tc=0.5,
-                       rates="paper", R=40.0, W=5.0, noise=0.01, seed=0, steps=5000)
+                       rates="unit", R=40.0, W=5.0, noise=0.01, seed=0, steps=5000)
 
 # Droplet impact on a flat wall: 384x384x192, walls at z = 0 and z = 191, 90 degree
 # contact angle (G_ads = 0), R = 40 at z = 50, U_z = -0.05, CS EOS at 0.55 T_c.

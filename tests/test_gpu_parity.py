@@ -244,7 +244,7 @@ def _window(f, z, y, x, h):
 
 @pytest.mark.parametrize("storage", ["fp32", "fp64"])
 def test_full_size_256_sampled_windows(L, storage):
-    """The benchmark workload at full size (256^3 D3Q19, CS at 0.5 T_c, paper rates,
+    """The benchmark workload at full size (256^3 D3Q19, CS at 0.5 T_c, non-viscous rates 1,
     +-1 % interface noise) in the benchmark's launch configuration: after 3 GPU steps the
     state is read back, one more GPU step is taken, and the oracle advances 12 sampled
     windows of 13^3 nodes by one step from the read-back state; the inner 9^3 of each
