@@ -202,3 +202,24 @@ def test_fused_launch_plan_overrides_and_errors(monkeypatch):
     with pytest.raises(lbm.LbmError) as ei:
         lbm.lbm_fused_plan(bad)
     assert ei.value.status == lbm.LBM_EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """The binding has no fallback: without the built HIP library every entry point raises."""
+    from paper_2306_16274_amd import lbm
+    monkeypatch.setattr(lbm, "_lib", None)
+    monkeypatch.setattr(lbm, "LIBRARY", str(tmp_path / "liblbm_hip.so"))
+    with pytest.raises(ImportError, match="missing"):
+        lbm.lbm_params_default()
+    with pytest.raises(ImportError, match="missing"):
+        lbm.Lattice(lbm.lbm_params_default())
+
+
+def test_product_package_does_not_touch_the_oracle():
+    """The package (binding, serving loop, impact driver) never imports the CPU oracle or the
+    test helpers: only tests, the smoke check and the benchmark's CPU baseline do."""
+    pkg = os.path.join(ROOT, "paper_2306_16274_amd")
+    for name in sorted(os.listdir(pkg)):
+        if name.endswith(".py"):
+            text = open(os.path.join(pkg, name)).read()
+            assert not re.search(r"^\s*(from|import)\s+(oracle|tests)\b", text, re.M), name
