@@ -242,16 +242,18 @@ def _window(f, z, y, x, h):
     return f[:, iz][:, :, iy][:, :, :, ix]
 
 
-@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+@pytest.mark.parametrize("storage", ["fp32", "fp64", "fp16"])
 def test_full_size_256_sampled_windows(L, storage):
     """The benchmark workload at full size (256^3 D3Q19, CS at 0.5 T_c, non-viscous rates 1,
     +-1 % interface noise) in the benchmark's launch configuration: after 3 GPU steps the
     state is read back, one more GPU step is taken, and the oracle advances 12 sampled
     windows of 13^3 nodes by one step from the read-back state; the inner 9^3 of each
-    window (unaffected by the window edge) must match."""
+    window (unaffected by the window edge) must match: FP64 to 1e-12 relative in rho, FP32
+    shifted storage to 1e-6, FP16 shifted storage (one rounding of every population to
+    11 significant bits) to 5e-3."""
     w = si.LAPLACE_256
     rv, rl = maxwell(w)
-    rho_ref = rv if storage == "fp32" else 0.0
+    rho_ref = 0.0 if storage == "fp64" else rv
     P = oracle_params(w)
     cx, cy, cz = w.droplet_centre()
     with L.Lattice(gpu_params(w, storage, rho_ref=rho_ref)) as lat:
@@ -277,7 +279,33 @@ def test_full_size_256_sampled_windows(L, storage):
         if storage == "fp64":
             assert rel_err(fg, fo) < 1e-12, (z, y, x)
     print(f"256^3 {storage}: worst sampled relative rho error after one step {worst:.2e}")
-    assert worst < (1e-12 if storage == "fp64" else 1e-6)
+    assert worst < {"fp64": 1e-12, "fp32": 1e-6, "fp16": 5e-3}[storage]
+
+
+def test_z_slab_256x256x32_sampled_windows(L):
+    """One GPU's z-slab of the benchmark workload if 256^3 were cut eight ways (256 x 256 x
+    32, periodic, droplet R = 12 at z = 16, FP32 shifted storage) in the launch configuration
+    the benchmark times for it (prefetching 256x4 tiles, 8-plane z-chunks, 256 workgroups):
+    one GPU step from a read-back state against the oracle on windows centred on the first
+    and last plane of every chunk, inside the droplet and on its interface."""
+    w = si.LAPLACE_256
+    ws = w.with_(nz=32, R=12.0, centre=(128.0, 128.0, 16))
+    rv, rl = maxwell(ws)
+    p = gpu_params(ws, "fp32", rho_ref=rv)
+    plan = L.lbm_fused_plan(p)
+    assert (plan["prefetch"], plan["z_chunk"], plan["workgroups"]) == (1, 8, 256), plan
+    cx, cy, cz = ws.droplet_centre()
+    with L.Lattice(p) as lat:
+        lat.init_droplet(cx, cy, cz, ws.R, ws.W, rl, rv, 0.0, 0.0, 0.0, ws.noise, ws.seed)
+        lat.step(3)
+        f3 = lat.get_populations()
+        lat.step(1)
+        f4 = lat.get_populations()
+    centres = [(z, int(cy), int(cx + ws.R)) for z in (0, 7, 8, 15, 16, 23, 24, 31)]
+    centres += [(cz, cy, cx), (cz + ws.R, cy, cx), (31, 255, 0), (8, 0, 128)]
+    er, ef = _sampled_window_errors(ws, f3, f4, centres)
+    print(f"256x256x32 slab fp32: worst relative rho {er:.2e}, worst |df| {ef:.2e}")
+    assert er < 1e-6
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "fp64"])
