@@ -350,7 +350,7 @@ __device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restr
                 const int sl = ez < 0 ? s0 : (ez > 0 ? s2 : s1);
                 pn[j] = ring[sl][ly + 1 + vel_y(j)][col(vel_x(j))];
             }
-            const NodeForce<R> nf = node_force<Q, R>(psi0, pn, P);
+            const NodeForce<R> nf = node_force<Q, R, GEOM != GEOM_NONE>(psi0, pn, P);
             collide<Q, R>(c, nf, P);
             const Off nb = (Off)(oxy[4] + z * nxy) * (Off)sizeof(T);
             if constexpr (NTS) {
@@ -662,7 +662,7 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
                 const int sl = ez < 0 ? s0 : (ez > 0 ? s2 : s1);
                 pn[j] = ring[sl][ly + 1 + vel_y(j)][col(vel_x(j))];
             }
-            const NodeForce<R> nf = node_force<Q, R>(psi0, pn, P);
+            const NodeForce<R> nf = node_force<Q, R, GEOM != GEOM_NONE>(psi0, pn, P);
             collide<Q, R>(cur, nf, P);
             const unsigned nb = (unsigned)(oxy[4] + z * nxy) * (unsigned)sizeof(T);
             if constexpr (NTS) {
@@ -814,7 +814,7 @@ __device__ __forceinline__ void fused_tile_pf64(const double* __restrict__ fin,
                 const int sl = ez < 0 ? s0 : (ez > 0 ? s2 : s1);
                 pn[j] = ring[sl][ly + 1 + vel_y(j)][col(vel_x(j))];
             }
-            const NodeForce<R> nf = node_force<Q, R>(psi0, pn, P);
+            const NodeForce<R> nf = node_force<Q, R, GEOM != GEOM_NONE>(psi0, pn, P);
             collide<Q, R>(cur, nf, P);
             const unsigned nb = (unsigned)(oxy[4] + z * nxy) * (unsigned)sizeof(T);
             if constexpr (NTS) {

@@ -112,7 +112,10 @@ struct NodeForce {
 
 // psi_nb[i] = psi(x + e_i) for i >= 1, negative where x + e_i is solid. A solid neighbour
 // takes psi of the node itself in F_int and Q_ab and counts in the wetting sum.
-template <int Q, typename R>
+// SOLIDS = false: the lattice has no solid node (psi_nb is never negative), so the solid
+// tests and the wetting sums drop out at compile time; the arithmetic of every remaining
+// term is unchanged, so both forms give bitwise equal results on such a lattice.
+template <int Q, typename R, bool SOLIDS = true>
 __device__ __forceinline__ NodeForce<R> node_force(R psi0, const R* psi_nb, const Phys<R>& P) {
     R ax = 0, ay = 0, az = 0;                 // sum w (psi_nb - psi0) e
     R qxx = 0, qyy = 0, qzz = 0, qxy = 0, qxz = 0, qyz = 0;
@@ -120,7 +123,7 @@ __device__ __forceinline__ NodeForce<R> node_force(R psi0, const R* psi_nb, cons
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const R w = R(wforce<Q>(i));
-        const bool solid = psi_nb[i] < R(0);
+        const bool solid = SOLIDS && psi_nb[i] < R(0);
         const R d = solid ? R(0) : psi_nb[i] - psi0;
         const int ex = vel_x(i), ey = vel_y(i), ez = vel_z(i);
         const R wd = w * d;
