@@ -115,8 +115,10 @@ struct NodeForce {
 // SOLIDS = false: the lattice has no solid node (psi_nb is never negative), so the solid
 // tests and the wetting sums drop out at compile time; the arithmetic of every remaining
 // term is unchanged, so both forms give bitwise equal results on such a lattice.
-template <int Q, typename R, bool SOLIDS = true>
-__device__ __forceinline__ NodeForce<R> node_force(R psi0, const R* psi_nb, const Phys<R>& P) {
+// WITH_Q = false: kappa = 0, so Q_ab of Eq. (B2) vanishes identically and its sums are
+// skipped (Q_ab = +0; the kappa-scaled products would be signed zeros).
+template <int Q, typename R, bool SOLIDS, bool WITH_Q>
+__device__ __forceinline__ NodeForce<R> node_force_sums(R psi0, const R* psi_nb, const Phys<R>& P) {
     R ax = 0, ay = 0, az = 0;                 // sum w (psi_nb - psi0) e
     R qxx = 0, qyy = 0, qzz = 0, qxy = 0, qxz = 0, qyz = 0;
     R sx = 0, sy = 0, sz = 0;                 // sum w s(x+e) e
@@ -130,12 +132,14 @@ __device__ __forceinline__ NodeForce<R> node_force(R psi0, const R* psi_nb, cons
         if (ex) ax += ex > 0 ? wd : -wd;
         if (ey) ay += ey > 0 ? wd : -wd;
         if (ez) az += ez > 0 ? wd : -wd;
-        if (ex) qxx += wd;
-        if (ey) qyy += wd;
-        if (ez) qzz += wd;
-        if (ex && ey) qxy += ex * ey > 0 ? wd : -wd;
-        if (ex && ez) qxz += ex * ez > 0 ? wd : -wd;
-        if (ey && ez) qyz += ey * ez > 0 ? wd : -wd;
+        if (WITH_Q) {
+            if (ex) qxx += wd;
+            if (ey) qyy += wd;
+            if (ez) qzz += wd;
+            if (ex && ey) qxy += ex * ey > 0 ? wd : -wd;
+            if (ex && ez) qxz += ex * ez > 0 ? wd : -wd;
+            if (ey && ez) qyz += ey * ez > 0 ? wd : -wd;
+        }
         const R ws = solid ? w : R(0);
         if (ex) sx += ex > 0 ? ws : -ws;
         if (ey) sy += ey > 0 ? ws : -ws;
@@ -150,10 +154,22 @@ __device__ __forceinline__ NodeForce<R> node_force(R psi0, const R* psi_nb, cons
     nf.Fy = gp * ay + ga * sy + P.bfy;
     nf.Fz = gp * az + ga * sz + P.bfz;
     nf.phi = P.G * P.G * (ax * ax + ay * ay + az * az);
-    const R kq = P.kappa * P.G * R(0.5) * psi0;   // Eq. (B2)
-    nf.Qxx = kq * qxx; nf.Qyy = kq * qyy; nf.Qzz = kq * qzz;
-    nf.Qxy = kq * qxy; nf.Qxz = kq * qxz; nf.Qyz = kq * qyz;
+    if (WITH_Q) {
+        const R kq = P.kappa * P.G * R(0.5) * psi0;   // Eq. (B2)
+        nf.Qxx = kq * qxx; nf.Qyy = kq * qyy; nf.Qzz = kq * qzz;
+        nf.Qxy = kq * qxy; nf.Qxz = kq * qxz; nf.Qyz = kq * qyz;
+    } else {
+        nf.Qxx = nf.Qyy = nf.Qzz = nf.Qxy = nf.Qxz = nf.Qyz = R(0);
+    }
     return nf;
+}
+// kappa is uniform over the launch, so the branch between the two forms is a scalar one.
+// Only lattices without solid nodes take it: with the solid tests in the loop, two copies
+// of it cost registers (walled and cylinder lattices ran 7-57 % slower).
+template <int Q, typename R, bool SOLIDS = true>
+__device__ __forceinline__ NodeForce<R> node_force(R psi0, const R* psi_nb, const Phys<R>& P) {
+    if (SOLIDS || P.kappa != R(0)) return node_force_sums<Q, R, SOLIDS, true>(psi0, psi_nb, P);
+    return node_force_sums<Q, R, false, false>(psi0, psi_nb, P);
 }
 
 // Raw moments k_mnp of the deviations (Eq. (2)); names follow the exponents.
