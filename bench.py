@@ -171,7 +171,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the lattice update "
-              "is benchmarked on a single MI355X; multi-GPU runs are not part of this build.",
+              "is benchmarked on a single MI355X; multi-GPU execution is not implemented.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -189,7 +189,7 @@ def main():
     r64 = run_gpu(w, "fp64", args.fp64_steps, max(2, args.warmup // 4), "zero", args.step_kernel)
     r16 = run_gpu(w, "fp16", args.fp16_steps, max(2, args.warmup // 4), args.rho_ref, args.step_kernel)
     # one GPU's share if the 256^3 lattice were cut into 8 z-slabs (periodic slab: the halo
-    # exchange between GPUs is not part of this build)
+    # exchange between GPUs is not implemented)
     slab = None
     if args.slab_steps > 0:
         ws = w.with_(nz=w.nz // 8, R=w.nz // 16 - 4.0, centre=(w.nx / 2, w.ny / 2, w.nz // 16))
