@@ -395,8 +395,8 @@ __global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ in,
     if (threadIdx.x < C) out[(long long)blockIdx.x * C + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// Plain streaming copy (measurement aid: the attainable read + write HBM bandwidth against
-// which the step kernels are judged): 16-byte elements, grid-stride, nontemporal hints.
+// Plain streaming copy (measurement aid: the attainable read + write HBM bandwidth that the
+// step kernels are compared with): 16-byte elements, grid-stride, nontemporal hints.
 typedef float lbm_f4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_copy_stream(const lbm_f4* __restrict__ a,
                                                      lbm_f4* __restrict__ b, long long n) {
