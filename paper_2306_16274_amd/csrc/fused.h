@@ -18,7 +18,9 @@
 //     XCDs in contiguous ranges (workgroup b runs on XCD b mod 8), so neighbouring tiles
 //     share an L2 and the halo re-reads stay on chip;
 //   * with a cylinder, solidity comes from one 32-bit link word per node (bit 0: the node,
-//     bit i: its neighbour x - e_i), not from a byte load per population;
+//     bit i: its neighbour x - e_i), not from a byte load per population; on a lattice
+//     without solid nodes the force sums drop their solid tests and wetting sums at compile
+//     time, and at kappa = 0 also the Q_ab sums (a scalar branch per launch);
 //   * addresses are 32-bit byte offsets from the buffer base below 4 GiB of populations,
 //     64-bit offsets (plain 64x4 / 64x8 tiles only) from there on, with the in-plane
 //     offsets of the 3x3 column neighbourhood computed once per thread.
@@ -170,7 +172,8 @@ __device__ __forceinline__ void st_off_nt(T* __restrict__ base, Off byte_off, T 
 }
 
 // How a kernel learns which nodes are solid: none (fully periodic), wall layers only
-// (decided from the coordinates, no memory traffic), or the byte mask (cylinder).
+// (decided from the coordinates, no memory traffic), or the link words built from the
+// solid mask (cylinder).
 enum { GEOM_NONE = 0, GEOM_WALLS = 1, GEOM_MASK = 2 };
 
 // Wall solidity of the coordinates c-1, c, c+1 (wrapped) along one axis, as bits 0..2.
