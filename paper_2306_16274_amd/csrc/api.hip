@@ -1,6 +1,6 @@
 // Host side of the C ABI declared in include/lbm.h: parameter validation, device
-// buffers, kernel dispatch over (lattice, storage type, solid/no-solid) and the host-only
-// coexistence solver.
+// buffers, dispatch over (lattice, storage type) to the step kernels (StepOps, compiled in
+// the step_q*_*.hip units), the diagnostics and the host-only coexistence solver.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -12,77 +12,15 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lbm.h"
-#include "fused.h"
+#include "ctx.h"
 #include "kernels.h"
+#include "misc_kernels.h"
 
-using namespace lbmk;
+thread_local std::string g_create_error;   // per calling thread
 
-struct lbm_ctx {
-    lbm_params p{};
-    int device = 0;
-    int Q = 19;
-    long long N = 0, stride = 0;
-    size_t elem = 4;               // bytes per stored population
-    void* f[2] = {nullptr, nullptr};
-    int cur = 0;
-    void* psi = nullptr;           // float64 (FP64 storage) or float32
-    uint8_t* solid = nullptr;
-    uint32_t* links = nullptr;     // link words of the fused step (cylinder geometries)
-    bool any_solid = false;
-    double* mom = nullptr;         // rho, u (3), p: 5 N doubles, allocated on first use
-    double* partial = nullptr;     // per-block partial sums (moments and health check)
-    long long partial_cap = 0;
-    double* dtot = nullptr;        // 5 device doubles
-    double* hhealth = nullptr;     // pinned: [min rho, non-finite flag]
-    hipEvent_t health_ev = nullptr;
-    bool health_pending = false;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    bool initialised = false;
-    bool failed = false;
-    int64_t steps = 0;
-    Phys<double> pd{};
-    Phys<float> pf{};
-    int fused_cfg = 0;             // index into kFusedCfgs
-    int cus = 256;                 // compute units of the device
-    bool addr64 = false;           // population buffer of 4 GiB or more: 64-bit offsets
-    std::string err;
-};
-
-static thread_local std::string g_create_error;   // per calling thread
-static int default_fused_cfg(const lbm_ctx* c);
-static bool needs_addr64(const lbm_params& p);
-
-static lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    if (c) c->err = buf; else g_create_error = buf;
-    return s;
+static int default_fused_cfg(const lbm_ctx* c) {
+    return fused_cfg_for(c->p.nx, (int)c->elem, c->Q, c->addr64);
 }
-
-#define HIPCHK(c, call)                                                                  \
-    do {                                                                                 \
-        hipError_t e_ = (call);                                                          \
-        if (e_ != hipSuccess)                                                            \
-            return fail((c), e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,       \
-                        "%s failed: %s", #call, hipGetErrorString(e_));                  \
-    } while (0)
-
-static long long plane_stride(long long N) { return (N + 63) / 64 * 64; }
-
-static size_t storage_bytes(int storage) {
-    return storage == LBM_FP64 ? 8 : storage == LBM_FP32 ? 4 : 2;
-}
-
-// Device buffers of a context are allocated and freed in stream order on the context's
-// stream (hipMallocAsync / hipFreeAsync), so creating or destroying one lattice never
-// waits for the work of other lattices.
-static hipError_t dmalloc(hipStream_t s, void** p, size_t bytes) { return hipMallocAsync(p, bytes, s); }
-static void dfree(hipStream_t s, void* p) { if (p) (void)hipFreeAsync(p, s); }
 
 // ---------------------------------------------------------------------------------------
 // Equations of state on the host (float64), for validation and the coexistence solver.
@@ -282,34 +220,6 @@ static lbm_status validate(const lbm_params& p) {
     return LBM_OK;
 }
 
-// ---------------------------------------------------------------------------------------
-// Launch helpers
-struct Launch { dim3 grid, block; };
-static Launch node_launch(const lbm_ctx* c) {
-    Launch L;
-    const int bx = c->p.nx >= 64 ? 64 : (c->p.nx >= 32 ? 32 : 16);
-    const int by = 256 / bx;
-    L.block = dim3(bx, by, 1);
-    L.grid = dim3((c->p.nx + bx - 1) / bx, (c->p.ny + by - 1) / by, c->p.nz);
-    return L;
-}
-static long long nblocks(const Launch& L) { return (long long)L.grid.x * L.grid.y * L.grid.z; }
-
-static Grid grid_of(const lbm_ctx* c) {
-    Grid g;
-    g.nx = c->p.nx; g.ny = c->p.ny; g.nz = c->p.nz; g.stride = c->stride;
-    g.walls = 0;
-    for (int a = 0; a < 3; ++a)
-        for (int s = 0; s < 2; ++s)
-            if (c->p.bc[a][s] == LBM_BC_WALL) g.walls |= 1 << (2 * a + s);
-    return g;
-}
-
-// Solid-node source of the fused kernels: none, wall layers from coordinates, or mask.
-static int geom_of(const lbm_ctx* c) {
-    if (!c->any_solid) return GEOM_NONE;
-    return c->p.cylinder ? GEOM_MASK : GEOM_WALLS;
-}
 
 // Solid nodes: wall layers on the faces marked LBM_BC_WALL and the nodes whose centre lies
 // in the x-aligned cylinder. The mask is written on the device (k_build_solid, the same
@@ -341,7 +251,7 @@ static long long count_fluid(const lbm_params& p, bool& any_solid) {
 }
 
 // Link words for the fused step on a solid mask (stream-ordered after the mask).
-static hipError_t build_links(lbm_ctx* c) {
+hipError_t build_links(lbm_ctx* c) {
     if (c->links) return hipSuccess;
     hipError_t e = dmalloc(c->stream, (void**)&c->links, (size_t)c->N * sizeof(uint32_t));
     if (e != hipSuccess) return e;
@@ -447,31 +357,6 @@ static lbm_status ensure_partial(lbm_ctx* c, long long n) {
     return LBM_OK;
 }
 
-template <int Q, typename T>
-static void launch_psi(lbm_ctx* c, const void* fin) {
-    using R = typename Arith<T>::type;
-    const Launch L = node_launch(c);
-    const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
-                                                         ? (const void*)&c->pd : (const void*)&c->pf);
-    if (c->any_solid)
-        hipLaunchKernelGGL((k_density_psi<Q, T, true>), L.grid, L.block, 0, c->stream,
-                           (const T*)fin, c->solid, (R*)c->psi, grid_of(c), P);
-    else
-        hipLaunchKernelGGL((k_density_psi<Q, T, false>), L.grid, L.block, 0, c->stream,
-                           (const T*)fin, c->solid, (R*)c->psi, grid_of(c), P);
-}
-
-template <int Q, typename T>
-static void launch_collide(lbm_ctx* c, const void* fin, void* fout) {
-    using R = typename Arith<T>::type;
-    const Launch L = node_launch(c);
-    const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
-                                                         ? (const void*)&c->pd : (const void*)&c->pf);
-    hipLaunchKernelGGL((k_collide<Q, T>), L.grid, L.block, 0, c->stream, (const T*)fin, (T*)fout,
-                       (const R*)c->psi, grid_of(c), P);
-}
-
-// Dispatch a templated functor over (Q, storage type).
 template <template <int, typename> class Fn, typename... A>
 static lbm_status dispatch(lbm_ctx* c, A... args) {
     if (c->Q == 19) {
@@ -493,67 +378,6 @@ struct KernelTimer {
 };
 static const char* const kTwoPassNames[] = {"k_density_psi", "k_collide"};
 static const char* const kFusedNames[] = {"k_step_fused"};
-
-// Tile configurations of the fused kernel. 256 x 2 full rows: the x-shifted pulls of a
-// row stay inside one workgroup and the halo is two rows; 64x8 or 64x4 tiles for other widths.
-
-// Population buffers of 4 GiB or more take 64-bit byte offsets, which only the plain 64x4
-// and 64x8 tiles are instantiated with (configurations 9 and 10).
-static bool needs_addr64(const lbm_params& p) {
-    const long long N = (long long)p.nx * p.ny * p.nz;
-    return (double)(p.lattice == 27 ? 27 : 19) * (double)plane_stride(N) *
-               (double)storage_bytes(p.storage) >= 4294967296.0;
-}
-
-// Launch configuration of the fused step for a lattice of width nx, element size elem and
-// lattice Q: the default of fused.h unless LBM_FUSED_CONFIG names a valid one (a full-row
-// configuration needs nx equal to its width; FP64 has no 320/384-wide instantiations; with
-// 64-bit offsets only configurations 9 and 10 exist).
-static int fused_cfg_for(int nx, int elem, int Q, bool addr64) {
-    if (const char* e = getenv("LBM_FUSED_CONFIG")) {      // tuning override
-        const int v = atoi(e);
-        if (v >= 0 && v < kNumFusedCfgs && (!kFusedCfgs[v].fullx || nx == kFusedCfgs[v].tx) &&
-            !(elem == 8 && kFusedCfgs[v].tx > 256) && (!addr64 || v == 9 || v == 10))
-            return v;
-    }
-    if (addr64) return elem == 4 ? 10 : 9;
-    return default_fused_cfg_index(nx, elem, Q);
-}
-static int default_fused_cfg(const lbm_ctx* c) {
-    return fused_cfg_for(c->p.nx, (int)c->elem, c->Q, c->addr64);
-}
-
-// Whether a configuration's prefetching tile fits in LDS for this lattice and element size
-// (the launch falls back to the plain tile of the same shape otherwise).
-static bool fused_prefetch_fits(const FusedCfg& f, int Q, int elem) {
-    if (!f.pf || !f.fullx) return false;
-    if (elem == 8) return fused_pf64_lds_bytes(Q, f.tx, f.ty) <= kLdsBytesPerCU;
-    return fused_pf_lds_bytes(Q, f.tx, f.ty) <= kLdsBytesPerCU;
-}
-
-// Planes per z-chunk, tile order and cache hints of a launch (defaults of fused.h, then the
-// LBM_FUSED_* tuning overrides), and the workgroup count.
-struct FusedPlan { int zc, remap, hints; long long workgroups; };
-static FusedPlan fused_plan(const lbm_params& p, int elem, int cfg, int cus) {
-    const FusedCfg& f = kFusedCfgs[cfg];
-    const long long tiles = (long long)((p.nx + f.tx - 1) / f.tx) * ((p.ny + f.ty - 1) / f.ty);
-    FusedPlan pl;
-    pl.zc = default_fused_zc(f, tiles, p.nz, cus);
-    pl.remap = default_fused_remap(f);
-    pl.hints = default_fused_hints(f, elem);
-    if (const char* e = getenv("LBM_FUSED_HINTS")) pl.hints = atoi(e);         // tuning override
-    if (const char* e = getenv("LBM_FUSED_ZC")) pl.zc = std::max(1, atoi(e));   // tuning override
-    if (const char* e = getenv("LBM_FUSED_REMAP")) pl.remap = atoi(e) != 0;    // tuning override
-    pl.zc = std::min(pl.zc, p.nz);
-    pl.workgroups = tiles * ((p.nz + pl.zc - 1) / pl.zc);
-    return pl;
-}
-static void fused_chunking(const lbm_ctx* c, int& zc, int& remap, int& hints) {
-    const FusedPlan pl = fused_plan(c->p, (int)c->elem, c->fused_cfg, c->cus);
-    zc = pl.zc;
-    remap = pl.remap;
-    hints = pl.hints;
-}
 
 extern "C" lbm_status lbm_fused_plan(const lbm_params* p, int32_t cus, lbm_fused_plan_t* out) {
     if (!p || !out) return fail(nullptr, LBM_EINVAL, "null argument");
@@ -579,133 +403,24 @@ extern "C" lbm_status lbm_fused_plan(const lbm_params* p, int32_t cus, lbm_fused
 }
 
 // Calls f(geometry, store hint) with both as compile-time constants (std::integral_constant):
-// the step kernels are instantiated per geometry and per store hint.
-template <typename F>
-static void with_geom_nts(const lbm_ctx* c, int hints, F&& f) {
-    using std::integral_constant;
-    const bool nt = (hints & kHintNtStore) != 0;
-    switch (geom_of(c)) {
-    case GEOM_NONE:
-        if (nt) f(integral_constant<int, GEOM_NONE>{}, integral_constant<bool, true>{});
-        else f(integral_constant<int, GEOM_NONE>{}, integral_constant<bool, false>{});
-        break;
-    case GEOM_WALLS:
-        if (nt) f(integral_constant<int, GEOM_WALLS>{}, integral_constant<bool, true>{});
-        else f(integral_constant<int, GEOM_WALLS>{}, integral_constant<bool, false>{});
-        break;
-    default:
-        if (nt) f(integral_constant<int, GEOM_MASK>{}, integral_constant<bool, true>{});
-        else f(integral_constant<int, GEOM_MASK>{}, integral_constant<bool, false>{});
-    }
-}
 
-template <int Q, typename T, int TX, int TY, bool FULLX, bool WIDE = false>
-static void launch_fused_cfg(lbm_ctx* c, const void* fin, void* fout) {
-    using R = typename Arith<T>::type;
-    const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
-                                                         ? (const void*)&c->pd : (const void*)&c->pf);
-    const int ntx = (c->p.nx + TX - 1) / TX, nty = (c->p.ny + TY - 1) / TY;
-    const long long tiles = (long long)ntx * nty;
-    int zc, remap, hints;
-    fused_chunking(c, zc, remap, hints);
-    const int nchunks = (c->p.nz + zc - 1) / zc;
-    const dim3 grid((unsigned)(tiles * nchunks)), block(TX * TY);
-    // 64-bit offsets are instantiated with plain stores only
-    with_geom_nts(c, WIDE ? (hints & ~kHintNtStore) : hints, [&](auto geom, auto nts) {
-        if constexpr (!WIDE || !decltype(nts)::value)
-            hipLaunchKernelGGL((k_step_fused<Q, T, decltype(geom)::value, TX, TY, FULLX,
-                                             decltype(nts)::value, WIDE>),
-                               grid, block, 0, c->stream, (const T*)fin, (T*)fout, c->links,
-                               grid_of(c), P, ntx, nty, zc, remap, hints);
-    });
-}
-
-// Full-row tiles with the LDS prefetch: k_step_fused_pf for 2- and 4-byte storage,
-// k_step_fused_pf64 (own populations only) for FP64, where the tile buffers fit in LDS; other
-// combinations run the plain full-row tiles.
-template <int Q, typename T, int TX, int TY>
-static void launch_fused_pf(lbm_ctx* c, const void* fin, void* fout) {
-    if constexpr (std::is_same<T, double>::value && fused_pf64_lds_bytes(Q, TX, TY) <= kLdsBytesPerCU) {
-        const int nty = (c->p.ny + TY - 1) / TY;
-        int zc, remap, hints;
-        fused_chunking(c, zc, remap, hints);
-        const int nchunks = (c->p.nz + zc - 1) / zc;
-        const dim3 grid((unsigned)(nty * nchunks)), block(TX * TY);
-        const double* f0 = (const double*)fin;
-        double* f1 = (double*)fout;
-        with_geom_nts(c, hints, [&](auto geom, auto nts) {
-            hipLaunchKernelGGL((k_step_fused_pf64<Q, decltype(geom)::value, TX, TY,
-                                                  decltype(nts)::value>),
-                               grid, block, 0, c->stream, f0, f1, c->links, grid_of(c), c->pd, zc,
-                               remap, hints);
-        });
-    } else if constexpr ((sizeof(T) == 4 || sizeof(T) == 2) && fused_pf_lds_bytes(Q, TX, TY) <= kLdsBytesPerCU) {
-        const int nty = (c->p.ny + TY - 1) / TY;
-        int zc, remap, hints;
-        fused_chunking(c, zc, remap, hints);
-        const int nchunks = (c->p.nz + zc - 1) / zc;
-        const dim3 grid((unsigned)(nty * nchunks)), block(TX * TY);
-        with_geom_nts(c, hints, [&](auto geom, auto nts) {
-            hipLaunchKernelGGL((k_step_fused_pf<Q, T, decltype(geom)::value, TX, TY,
-                                                decltype(nts)::value>),
-                               grid, block, 0, c->stream, (const T*)fin, (T*)fout, c->links,
-                               grid_of(c), c->pf, zc, remap, hints);
-        });
-    } else {
-        launch_fused_cfg<Q, T, TX, TY, true>(c, fin, fout);
-    }
-}
-
-// 320- and 384-wide full rows (2-row tiles) for 2- and 4-byte storage only: FP64 needs more
-// VGPRs than 640 or 768 threads leave a lane (12.3 vs 9.4 GLUPS, 32x8 vs 384x2 at 384^2 x 160),
-// so FP64 is not instantiated here and never selected (default_fused_cfg).
-template <int Q, typename T>
-static void launch_fused_wide(lbm_ctx* c, const void* fin, void* fout) {
-    if constexpr (sizeof(T) != 8) {
-        switch (c->fused_cfg) {
-        case 5: launch_fused_cfg<Q, T, 320, 2, true>(c, fin, fout); break;
-        case 6: launch_fused_pf<Q, T, 320, 2>(c, fin, fout); break;
-        case 7: launch_fused_cfg<Q, T, 384, 2, true>(c, fin, fout); break;
-        default: launch_fused_pf<Q, T, 384, 2>(c, fin, fout); break;
-        }
-    }
-}
-
-template <int Q, typename T>
-static void launch_fused(lbm_ctx* c, const void* fin, void* fout) {
-    if (c->addr64) {                       // population buffer of 4 GiB or more
-        if (c->fused_cfg == 9) launch_fused_cfg<Q, T, 64, 4, false, true>(c, fin, fout);
-        else launch_fused_cfg<Q, T, 64, 8, false, true>(c, fin, fout);
-        return;
-    }
-    switch (c->fused_cfg) {
-    case 1: launch_fused_cfg<Q, T, 256, 2, true>(c, fin, fout); break;
-    case 2: launch_fused_cfg<Q, T, 256, 4, true>(c, fin, fout); break;
-    case 3: launch_fused_pf<Q, T, 256, 4>(c, fin, fout); break;
-    case 4: launch_fused_pf<Q, T, 256, 2>(c, fin, fout); break;
-    case 5: case 6: case 7: case 8: launch_fused_wide<Q, T>(c, fin, fout); break;
-    case 9: launch_fused_cfg<Q, T, 64, 4, false>(c, fin, fout); break;
-    case 10: launch_fused_cfg<Q, T, 64, 8, false>(c, fin, fout); break;
-    default: launch_fused_cfg<Q, T, 32, 8, false>(c, fin, fout); break;
-    }
-}
-
+// One time step of the context's schedule (fused, or the two passes) from the current
+// buffer into the other, with an event pair around each kernel when timed.
 template <int Q, typename T>
 struct StepFn {
-    static lbm_status run(lbm_ctx* c, int64_t nsteps, KernelTimer* tm = nullptr) {
+    static lbm_status run(lbm_ctx* c, int64_t nsteps, KernelTimer* tm) {
         const bool fused = c->p.step_kernel == LBM_STEP_FUSED;
         for (int64_t s = 0; s < nsteps; ++s) {
+            if (tm) HIPCHK(c, hipEventRecord(tm->ev[0], c->stream));
             if (fused) {
-                if (tm) HIPCHK(c, hipEventRecord(tm->ev[0], c->stream));
-                launch_fused<Q, T>(c, c->f[c->cur], c->f[1 - c->cur]);
+                StepOps<Q, T>::fused(c, c->f[c->cur], c->f[1 - c->cur]);
                 if (tm) HIPCHK(c, hipEventRecord(tm->ev[1], c->stream));
                 if (tm) tm->nk = 1;
             } else {
-                if (tm) HIPCHK(c, hipEventRecord(tm->ev[0], c->stream));
-                launch_psi<Q, T>(c, c->f[c->cur]);
+                StepOps<Q, T>::psi(c, c->f[c->cur]);
                 if (tm) HIPCHK(c, hipEventRecord(tm->ev[1], c->stream));
                 if (tm) HIPCHK(c, hipEventRecord(tm->ev[2], c->stream));
-                launch_collide<Q, T>(c, c->f[c->cur], c->f[1 - c->cur]);
+                StepOps<Q, T>::collide(c, c->f[c->cur], c->f[1 - c->cur]);
                 if (tm) HIPCHK(c, hipEventRecord(tm->ev[3], c->stream));
                 if (tm) tm->nk = 2;
             }
@@ -719,26 +434,35 @@ struct StepFn {
             }
             c->cur = 1 - c->cur;
             c->steps++;
-            if (c->p.reduce_every > 0 && c->steps % c->p.reduce_every == 0) {
-                using R = typename Arith<T>::type;
-                const Launch L = node_launch(c);
-                lbm_status st = ensure_partial(c, 2 * nblocks(L));
-                if (st != LBM_OK) return st;
-                hipLaunchKernelGGL((k_health<Q, T>), L.grid, L.block, 0, c->stream,
-                                   (const T*)c->f[c->cur], (const R*)c->psi, c->partial,
-                                   grid_of(c), c->p.rho_ref);
-                hipLaunchKernelGGL(k_health_final, dim3(1), dim3(256), 0, c->stream,
-                                   c->partial, nblocks(L), c->dtot + 5);
-                HIPCHK(c, hipMemcpyAsync(c->hhealth, c->dtot + 5, 2 * sizeof(double),
-                                         hipMemcpyDeviceToHost, c->stream));
-                HIPCHK(c, hipEventRecord(c->health_ev, c->stream));
-                c->health_pending = true;
-            }
         }
         HIPCHK(c, hipGetLastError());
         return LBM_OK;
     }
 };
+
+// Health check of the current state (k_health over the fluid nodes of the solid mask, then
+// one block), its result copied to pinned host memory and marked by health_ev; read by
+// poll_health.
+template <int Q, typename T>
+struct HealthFn {
+    static lbm_status run(lbm_ctx* c) {
+        const Launch L = node_launch(c);
+        lbm_status st = ensure_partial(c, 2 * nblocks(L));
+        if (st != LBM_OK) return st;
+        hipLaunchKernelGGL((k_health<Q, T>), L.grid, L.block, 0, c->stream,
+                           (const T*)c->f[c->cur], c->solid, c->partial, grid_of(c), c->p.rho_ref);
+        hipLaunchKernelGGL(k_health_final, dim3(1), dim3(256), 0, c->stream, c->partial,
+                           nblocks(L), c->dtot + 5);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(c->hhealth, c->dtot + 5, 2 * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipEventRecord(c->health_ev, c->stream));
+        c->health_pending = true;
+        return LBM_OK;
+    }
+};
+
+lbm_status enqueue_health(lbm_ctx* c) { return dispatch<HealthFn>(c); }
 
 // Read the last health check if it has completed (wait = block until it has).
 static lbm_status poll_health(lbm_ctx* c, bool wait) {
@@ -754,6 +478,24 @@ static lbm_status poll_health(lbm_ctx* c, bool wait) {
     return LBM_OK;
 }
 
+// nsteps steps, with a health check after every step whose count is a multiple of
+// reduce_every (if > 0).
+static lbm_status run_steps(lbm_ctx* c, int64_t nsteps, KernelTimer* tm) {
+    const int64_t every = c->p.reduce_every;
+    while (nsteps > 0) {
+        int64_t n = nsteps;
+        if (every > 0) n = std::min<int64_t>(n, every - c->steps % every);
+        lbm_status st = dispatch<StepFn>(c, n, tm);
+        if (st != LBM_OK) return st;
+        nsteps -= n;
+        if (every > 0 && c->steps % every == 0) {
+            st = enqueue_health(c);
+            if (st != LBM_OK) return st;
+        }
+    }
+    return LBM_OK;
+}
+
 extern "C" lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
     if (!c) return fail(nullptr, LBM_EINVAL, "null context");
     if (nsteps < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
@@ -762,7 +504,7 @@ extern "C" lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
     HIPCHK(c, hipSetDevice(c->device));
     lbm_status st = poll_health(c, false);
     if (st != LBM_OK) return st;
-    return dispatch<StepFn>(c, nsteps, (KernelTimer*)nullptr);
+    return run_steps(c, nsteps, nullptr);
 }
 
 extern "C" lbm_status lbm_kernel_times(lbm_ctx* c, int64_t nsteps, double* avg_ms,
@@ -774,7 +516,7 @@ extern "C" lbm_status lbm_kernel_times(lbm_ctx* c, int64_t nsteps, double* avg_m
     HIPCHK(c, hipSetDevice(c->device));
     KernelTimer tm{};
     for (int k = 0; k < 2 * KernelTimer::kMax; ++k) HIPCHK(c, hipEventCreate(&tm.ev[k]));
-    lbm_status st = dispatch<StepFn>(c, nsteps, &tm);
+    lbm_status st = run_steps(c, nsteps, &tm);
     for (int k = 0; k < 2 * KernelTimer::kMax; ++k) (void)hipEventDestroy(tm.ev[k]);
     if (st != LBM_OK) return st;
     const int n = std::min<int>(tm.nk, cap);
@@ -799,8 +541,7 @@ struct InitFieldsFn {
     static lbm_status run(lbm_ctx* c, const double* drho, const double* du) {
         using R = typename Arith<T>::type;
         const Launch L = node_launch(c);
-        const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
-                                                             ? (const void*)&c->pd : (const void*)&c->pf);
+        const Phys<R>& P = phys_of<R>(c);
         c->cur = 0;
         hipLaunchKernelGGL((k_init_fields<Q, T>), L.grid, L.block, 0, c->stream, drho, du,
                            (T*)c->f[0], c->solid, grid_of(c), P);
@@ -911,9 +652,8 @@ struct MomentsFn {
         const Launch L = node_launch(c);
         st = ensure_partial(c, 5 * nblocks(L));
         if (st != LBM_OK) return st;
-        const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
-                                                             ? (const void*)&c->pd : (const void*)&c->pf);
-        launch_psi<Q, T>(c, c->f[c->cur]);
+        const Phys<R>& P = phys_of<R>(c);
+        StepOps<Q, T>::psi(c, c->f[c->cur]);
         double* drho = c->mom;
         double* du = c->mom + c->N;
         double* dp = c->mom + 4 * c->N;
@@ -954,9 +694,8 @@ struct LiquidFn {
         if (st != LBM_OK) return st;
         double* plane = c->partial + 3 * nb;       // nz rows: liquid, in contact, volume
         double* tot = plane + 3 * nz;
-        const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
-                                                             ? (const void*)&c->pd : (const void*)&c->pf);
-        launch_psi<Q, T>(c, c->f[c->cur]);
+        const Phys<R>& P = phys_of<R>(c);
+        StepOps<Q, T>::psi(c, c->f[c->cur]);
         hipLaunchKernelGGL((k_liquid_stats<Q, T>), L.grid, L.block, 0, c->stream,
                            (const T*)c->f[c->cur], (const R*)c->psi, c->partial, grid_of(c),
                            P.rho_ref, threshold, rho_v, rho_l, reach);
@@ -1025,231 +764,3 @@ extern "C" lbm_status lbm_copy_bandwidth(int64_t bytes, int32_t reps, double* gb
     if (s) (void)hipStreamDestroy(s);
     return st;
 }
-
-// ---------------------------------------------------------------------------------------
-// Batched stepping of many contexts: one launch per step over every member's tiles
-// (k_step_fused_batch), steps_per_launch launches captured once into a HIP graph.
-// Tile shapes of the batched kernel (index lbm_batch::tile) and the z-chunk depth.
-constexpr int kBatchTiles[2][2] = {{64, 4}, {32, 8}};
-constexpr int kBatchZC = 16;
-
-struct lbm_batch {
-    std::vector<lbm_ctx*> ctx;
-    int steps_per_launch = 2;
-    int storage = LBM_FP32;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    void* table[2] = {nullptr, nullptr};  // device DomainDesc arrays: even / odd steps
-    std::vector<char> host_table[2];      // their sources (alive until the copies are done)
-    bool ran = false;
-    long long blocks = 0;
-    int geom = GEOM_WALLS;                // GEOM_MASK if any member has a cylinder
-    int tile = 0;                         // index into kBatchTiles
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipEvent_t done = nullptr;
-    std::vector<hipEvent_t> ready;
-};
-
-static thread_local std::string g_batch_error;    // per calling thread
-static lbm_status batch_fail(lbm_status s, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_batch_error = buf;
-    return s;
-}
-#define BCHK(call) do { hipError_t e_ = (call); if (e_ != hipSuccess)                        \
-    return batch_fail(e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "%s failed: %s",  \
-                      #call, hipGetErrorString(e_)); } while (0)
-
-template <typename T, int TX, int TY>
-static void launch_batch(const lbm_batch* b, hipStream_t s, const void* table, bool pf, bool nt,
-                         int remap) {
-    const dim3 grid((unsigned)b->blocks), block(TX * TY);
-    const DomainDesc<T>* tb = (const DomainDesc<T>*)table;
-    const int nd = (int)b->ctx.size();
-    auto go = [&](auto geom, auto nts) {
-        constexpr int G = decltype(geom)::value;
-        constexpr bool N = decltype(nts)::value;
-        if constexpr (sizeof(T) == 4) {
-            if (pf) {
-                hipLaunchKernelGGL((k_step_fused_batch_pf<19, T, G, TX, TY, N>), grid, block, 0, s,
-                                   tb, nd, remap);
-                return;
-            }
-        }
-        hipLaunchKernelGGL((k_step_fused_batch<19, T, G, TX, TY, N>), grid, block, 0, s, tb, nd, remap);
-    };
-    using std::integral_constant;
-    if (b->geom == GEOM_MASK) {
-        if (nt) go(integral_constant<int, GEOM_MASK>{}, integral_constant<bool, true>{});
-        else go(integral_constant<int, GEOM_MASK>{}, integral_constant<bool, false>{});
-    } else {
-        if (nt) go(integral_constant<int, GEOM_WALLS>{}, integral_constant<bool, true>{});
-        else go(integral_constant<int, GEOM_WALLS>{}, integral_constant<bool, false>{});
-    }
-}
-
-template <typename T>
-static lbm_status build_tables(lbm_batch* b) {
-    using R = typename Arith<T>::type;
-    std::vector<DomainDesc<T>> t[2];
-    long long block0 = 0;
-    const int TX = kBatchTiles[b->tile][0], TY = kBatchTiles[b->tile][1];
-    for (lbm_ctx* c : b->ctx) {
-        const int ntx = (c->p.nx + TX - 1) / TX, nty = (c->p.ny + TY - 1) / TY;
-        int zc = kBatchZC;
-        if (const char* e = getenv("LBM_BATCH_ZC")) zc = std::max(1, atoi(e));    // tuning override
-        zc = std::min(zc, c->p.nz);
-        const long long nb = (long long)ntx * nty * ((c->p.nz + zc - 1) / zc);
-        const Phys<R>& P = *reinterpret_cast<const Phys<R>*>(std::is_same<R, double>::value
-                                                             ? (const void*)&c->pd : (const void*)&c->pf);
-        for (int par = 0; par < 2; ++par) {
-            DomainDesc<T> d{};
-            d.fin = (const T*)c->f[(c->cur + par) & 1];
-            d.fout = (T*)c->f[(c->cur + par + 1) & 1];
-            d.links = c->links;
-            d.g = grid_of(c);
-            d.P = P;
-            d.ntx = ntx; d.nty = nty; d.zc = zc; d.block0 = (int)block0;
-            t[par].push_back(d);
-        }
-        block0 += nb;
-    }
-    if (block0 > 0x7fffffffLL) return batch_fail(LBM_EINVAL, "batch too large");
-    b->blocks = block0;
-    const size_t bytes = t[0].size() * sizeof(DomainDesc<T>);
-    for (int par = 0; par < 2; ++par) {
-        b->host_table[par].resize(bytes);
-        std::memcpy(b->host_table[par].data(), t[par].data(), bytes);
-        BCHK(dmalloc(b->stream, &b->table[par], bytes));
-        BCHK(hipMemcpyAsync(b->table[par], b->host_table[par].data(), bytes, hipMemcpyHostToDevice,
-                            b->stream));
-    }
-    // capture steps_per_launch launches, alternating the two tables, on a private stream
-    hipStream_t cap = nullptr;
-    BCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    hipError_t ce = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (ce != hipSuccess) { (void)hipStreamDestroy(cap); BCHK(ce); }
-    // Plain tiles: on serving mixes of box sizes (rows not 128-byte aligned) they beat the
-    // prefetching tiles (19.2 vs 17.9 GLUPS) and 32x8 tiles (16.2); LBM_BATCH_PF=1 selects
-    // the prefetching tiles for 4-byte storage (tuning).
-    // Nontemporal stores when every member's rows are whole 128-byte lines (serving shapes,
-    // GLUPS, nontemporal vs plain: 8x128^3 23.0 vs 22.6, 32x64^3 26.7 vs 26.2, 2x192^3 23.5
-    // vs 23.2; 24 mixed sizes, mostly unaligned rows: 18.1 vs 19.1).
-    bool pf = false, nt = true;
-    for (const lbm_ctx* c : b->ctx) nt = nt && ((long long)c->p.nx * (long long)c->elem) % 128 == 0;
-    if (const char* e = getenv("LBM_BATCH_PF")) pf = sizeof(T) == 4 && atoi(e) != 0;
-    if (const char* e = getenv("LBM_BATCH_NT")) nt = atoi(e) != 0;              // tuning override
-    // XCD-contiguous tile ranges, as for single lattices (GLUPS, on / off: 8x128^3 24.3 / 23.0,
-    // 16x96^3 23.3 / 21.3, 32x64^3 27.8 / 26.3, 2x192^3 26.0 / 23.5, 24 mixed 19.9 / 19.1)
-    int remap = 1;
-    if (const char* e = getenv("LBM_BATCH_REMAP")) remap = atoi(e) != 0;       // tuning override
-    for (int s = 0; s < b->steps_per_launch; ++s) {
-        if (b->tile == 0)
-            launch_batch<T, kBatchTiles[0][0], kBatchTiles[0][1]>(b, cap, b->table[s & 1], pf, nt, remap);
-        else
-            launch_batch<T, kBatchTiles[1][0], kBatchTiles[1][1]>(b, cap, b->table[s & 1], pf, nt, remap);
-    }
-    ce = hipStreamEndCapture(cap, &b->graph);
-    (void)hipStreamDestroy(cap);
-    BCHK(ce);
-    BCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-    return LBM_OK;
-}
-
-static void batch_free(lbm_batch* b) {
-    if (!b) return;
-    // wait for this batch's own replays only (work queued after them keeps running)
-    if (b->ran && b->done) (void)hipEventSynchronize(b->done);
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    if (b->stream)
-        for (void* t : b->table) dfree(b->stream, t);
-    if (b->done) (void)hipEventDestroy(b->done);
-    for (hipEvent_t e : b->ready) if (e) (void)hipEventDestroy(e);
-    if (b->own_stream && b->stream) {
-        (void)hipStreamSynchronize(b->stream);
-        (void)hipStreamDestroy(b->stream);
-    }
-}
-
-extern "C" lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, int32_t steps_per_launch,
-                                       void* stream, lbm_batch** out) {
-    if (!ctxs || !out || n < 1) return batch_fail(LBM_EINVAL, "need at least one context");
-    if (steps_per_launch < 2 || steps_per_launch % 2)
-        return batch_fail(LBM_EINVAL, "steps_per_launch must be even and >= 2");
-    *out = nullptr;
-    const int storage = ctxs[0]->p.storage;
-    for (int i = 0; i < n; ++i) {
-        const lbm_ctx* c = ctxs[i];
-        if (!c) return batch_fail(LBM_EINVAL, "null context");
-        if (c->device != ctxs[0]->device) return batch_fail(LBM_EINVAL, "members must share a device");
-        if (c->Q != 19) return batch_fail(LBM_EINVAL, "batched stepping supports D3Q19");
-        if (c->p.storage != storage || storage == LBM_FP16)
-            return batch_fail(LBM_EINVAL, "members must share FP32 or FP64 storage");
-        if (!c->initialised || c->failed) return batch_fail(LBM_ESTATE, "member %d not initialised or failed", i);
-        if ((double)c->Q * (double)c->stride * (double)c->elem >= 4294967296.0)
-            return batch_fail(LBM_EINVAL, "member %d has a population buffer of 4 GiB or more", i);
-        for (int j = 0; j < i; ++j)
-            if (ctxs[j] == c) return batch_fail(LBM_EINVAL, "context %d appears twice", i);
-    }
-    lbm_batch* b = new (std::nothrow) lbm_batch();
-    if (!b) return batch_fail(LBM_ENOMEM, "host allocation failed");
-    b->ctx.assign(ctxs, ctxs + n);
-    b->steps_per_launch = steps_per_launch;
-    b->storage = storage;
-    for (int i = 0; i < n; ++i)
-        if (ctxs[i]->p.cylinder && ctxs[i]->any_solid) b->geom = GEOM_MASK;
-    if (const char* e = getenv("LBM_BATCH_TILE")) b->tile = atoi(e) == 1 ? 1 : 0;   // tuning override
-    auto bail = [&](lbm_status s) { batch_free(b); delete b; return s; };
-    hipError_t e = hipSetDevice(ctxs[0]->device);
-    if (e == hipSuccess) {
-        if (stream) b->stream = (hipStream_t)stream;
-        else { e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking); b->own_stream = true; }
-    }
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
-    b->ready.assign(n, nullptr);
-    for (int i = 0; e == hipSuccess && i < n; ++i) e = hipEventCreateWithFlags(&b->ready[i], hipEventDisableTiming);
-    // a batch on the solid mask reads every member's link words (members without a
-    // cylinder get them here, from their wall mask)
-    for (int i = 0; e == hipSuccess && b->geom == GEOM_MASK && i < n; ++i) e = build_links(ctxs[i]);
-    if (e != hipSuccess) { batch_fail(LBM_EDEVICE, "batch setup failed: %s", hipGetErrorString(e)); return bail(LBM_EDEVICE); }
-    lbm_status st = storage == LBM_FP64 ? build_tables<double>(b) : build_tables<float>(b);
-    if (st != LBM_OK) return bail(st);
-    *out = b;
-    return LBM_OK;
-}
-
-extern "C" lbm_status lbm_batch_run(lbm_batch* b, int64_t nlaunch) {
-    if (!b) return batch_fail(LBM_EINVAL, "null batch");
-    if (nlaunch < 0) return batch_fail(LBM_EINVAL, "nlaunch must be >= 0");
-    for (lbm_ctx* c : b->ctx)
-        if (c->failed) return batch_fail(LBM_ESTATE, "a member failed its health check");
-    BCHK(hipSetDevice(b->ctx[0]->device));
-    // order after each member's stream, replay, then order each member's stream after us
-    for (size_t i = 0; i < b->ctx.size(); ++i) {
-        BCHK(hipEventRecord(b->ready[i], b->ctx[i]->stream));
-        BCHK(hipStreamWaitEvent(b->stream, b->ready[i], 0));
-    }
-    for (int64_t k = 0; k < nlaunch; ++k) BCHK(hipGraphLaunch(b->exec, b->stream));
-    BCHK(hipEventRecord(b->done, b->stream));
-    b->ran = true;
-    for (lbm_ctx* c : b->ctx) {
-        BCHK(hipStreamWaitEvent(c->stream, b->done, 0));
-        c->steps += nlaunch * b->steps_per_launch;      // even count: c->cur unchanged
-    }
-    return LBM_OK;
-}
-
-extern "C" lbm_status lbm_batch_destroy(lbm_batch* b) {
-    if (!b) return LBM_OK;
-    batch_free(b);
-    delete b;
-    return LBM_OK;
-}
-
-extern "C" const char* lbm_batch_last_error(void) { return g_batch_error.c_str(); }
