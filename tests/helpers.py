@@ -72,3 +72,36 @@ def abs_err(a, b, mask=None):
     if mask is not None:
         a, b = a[..., mask], b[..., mask]
     return float(np.max(np.abs(a - b)))
+
+
+def totals_err(gpu_totals, f, P, solid=None):
+    """Largest error of the GPU's five totals (mass, momentum, kinetic energy) against the
+    oracle's for the state f, each scaled by the sum of the magnitudes it adds up (mass,
+    sum |rho u_a|, E_k), so that near-zero momentum totals are compared at the rounding
+    level of their terms."""
+    from oracle import lbm as olbm
+    want = olbm.totals(f, P, solid)
+    rho, u, _, mac = olbm.moments(f, P, solid)
+    fl = ~mac["solid"]
+    scale = np.array([want[0]] + [np.abs(rho * u[a])[fl].sum() for a in range(3)] + [want[4]])
+    scale = np.where(scale > 0, scale, 1.0)
+    return float(np.max(np.abs(np.asarray(gpu_totals) - want) / scale))
+
+
+def piecewise_slab(w, z_a, z_b, W, f_amp=0.02, seed=3):
+    """Oracle populations of a liquid slab z_a < z < z_b between the piecewise EOS's
+    coexistence densities (rho_l = 1, rho_v = 0.001), a planar tanh profile of width W
+    (Eq. (21)) on each face, at rest, with multiplicative noise amp U(-1, 1) on every
+    population; and the oracle params. A slab is the stationary state of a planar
+    interface, so the liquid stays above rho_2 and the vapour far from it below rho_1."""
+    import synth_inputs as si
+    from oracle import lbm as olbm
+    P = oracle_params(w)
+    solid = olbm.solid_mask(P)
+    z = np.arange(w.nz, dtype=np.float64).reshape(-1, 1, 1)
+    d = np.minimum(z - z_a, z_b - z)
+    rho = np.broadcast_to(0.5 * 1.001 + 0.5 * 0.999 * np.tanh(2.0 * d / W), w.shape).copy()
+    f = olbm.equilibrium_populations(P, rho, np.zeros((3,) + w.shape), solid)
+    f = f * si.random_factors(w.Q, w.shape, seed=seed, amp=f_amp)
+    f[:, solid] = 0.0
+    return P, solid, f

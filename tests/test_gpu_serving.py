@@ -112,3 +112,50 @@ def test_serving_results_same_alone_and_in_the_mix(L):
         assert r["mass"] == s["mass"] and r["spread_diameter"] == s["spread_diameter"], r["id"]
         assert r["liquid_volume"] == s["liquid_volume"], r["id"]
         assert r["finite"]
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_batch_members_match_the_oracle(L, storage):
+    """Every member of a batch against the FP64 oracle (not only against its own single-
+    lattice run): three small lattices (walls, a cylinder with wetting, kappa, a ragged
+    shape) from seeded random states, one batch run of 10 steps. FP64 populations to 1e-13
+    absolute; FP32 shifted storage to 1e-5 relative in rho and 1e-4 absolute in u."""
+    from oracle import lbm as olbm
+    from tests.helpers import abs_err, oracle_params, rel_err
+    ws = [si.Workload("a", 19, 20, 16, 12, T_over_Tc=0.6, walls=("z_lo", "z_hi"), G_ads=0.1,
+                      kappa=0.3, nu=0.05),
+          si.Workload("b", 19, 24, 13, 10, T_over_Tc=0.7, nu=0.08),
+          si.Workload("c", 19, 17, 22, 14, T_over_Tc=0.6, walls=("z_lo",), G_ads=-0.1,
+                      cylinder=(11.0, 4.0, 2.0), nu=0.1)]
+    lats, refs = [], []
+    for k, w in enumerate(ws):
+        rho, u = si.random_fields(w.shape, seed=40 + k, rho_lo=0.05, rho_hi=0.4)
+        P = oracle_params(w)
+        solid = olbm.solid_mask(P)
+        f0 = olbm.equilibrium_populations(P, rho, u, solid)
+        f0 = f0 * si.random_factors(19, w.shape, seed=40 + k, amp=0.02)
+        f0[:, solid] = 0.0
+        rv, _ = maxwell(w)
+        lat = L.Lattice(gpu_params(w, storage, rho_ref=rv if storage == "fp32" else 0.0))
+        lat.set_populations(f0)
+        lats.append(lat)
+        refs.append((P, solid, olbm.run(f0, P, 10, solid)))
+    b = L.lbm_batch_create([lat.ctx for lat in lats], 10)
+    try:
+        L.lbm_batch_run(b, 1)
+    finally:
+        L.lbm_batch_destroy(b)
+    for lat, (P, solid, fo), w in zip(lats, refs, ws):
+        fl = ~solid
+        if storage == "fp64":
+            g = lat.get_populations()
+            err = abs_err(g, fo)
+            print(f"batch member {w.name} fp64: max |df| {err:.2e}")
+            assert err < 1e-13, w.name
+        m = lat.moments()
+        ro, uo, _, _ = olbm.moments(fo, P, solid)
+        er, eu = rel_err(m["rho"], ro, fl), abs_err(m["u"], uo, fl)
+        print(f"batch member {w.name} {storage}: rho rel {er:.2e}, u abs {eu:.2e}")
+        assert er < (1e-12 if storage == "fp64" else 1e-5), w.name
+        assert eu < (1e-13 if storage == "fp64" else 1e-4), w.name
+        lat.close()

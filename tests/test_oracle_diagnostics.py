@@ -59,3 +59,35 @@ def test_liquid_stats_flat_film_on_wall():
     assert list(olbm.liquid_stats(f, P, 0.5 * (rv + rl), rv, rl, solid, reach=2)[1][:5]) == [0, 48, 48, 0, 0]
     assert list(olbm.liquid_stats(f, P, 0.5 * (rv + rl), rv, rl, solid, reach=3)[1][:5]) == [0, 48, 48, 48, 0]
     assert abs(vol - 3 * 48) < 1e-9
+
+
+@pytest.mark.parametrize("Q", [19, 27])
+def test_totals_of_a_uniform_moving_state_closed_form(Q):
+    """The five totals of a uniform state rho0, u0 (equilibrium populations, periodic box,
+    no interaction force since psi is uniform) with a uniform body force b: by Eq. (10) the
+    momentum of each node is sum_i f_i e_i + b/2 = rho0 u0 + b/2, so the totals are
+    N rho0, N (rho0 u0 + b/2) and N |rho0 u0 + b/2|^2 / (2 rho0) (kinetic energy
+    rho |u|^2 / 2 with u the momentum over rho). A dropped 1/2 in the kinetic energy, a
+    missing F/2 or a wrong component would each break one of these."""
+    b = np.array([2e-4, -3e-4, 5e-4])
+    P = _params(Q, 5, 4, 3, body_force=tuple(b))
+    rho0, u0 = 0.27, np.array([0.03, -0.02, 0.05])
+    rho = np.full(P.shape, rho0)
+    u = np.broadcast_to(u0.reshape(3, 1, 1, 1), (3,) + P.shape).copy()
+    f = olbm.equilibrium_populations(P, rho, u)
+    N = P.nx * P.ny * P.nz
+    j = rho0 * u0 + 0.5 * b
+    want = np.array([N * rho0, *(N * j), N * float(j @ j) / (2 * rho0)])
+    got = olbm.totals(f, P)
+    assert np.allclose(got, want, rtol=1e-13, atol=0.0), (got, want)
+
+
+def test_totals_exclude_solid_nodes():
+    """Totals run over fluid nodes only: a uniform resting state between two walls has the
+    mass of its fluid layers (nz - 2 planes) and no momentum or kinetic energy."""
+    P = _params(19, 4, 3, 6, walls={"z_lo": True, "z_hi": True})
+    rho = np.full(P.shape, 0.3)
+    f = olbm.equilibrium_populations(P, rho, np.zeros((3,) + P.shape))
+    got = olbm.totals(f, P)
+    assert abs(got[0] - 0.3 * 4 * 3 * 4) < 1e-13
+    assert np.all(np.abs(got[1:]) < 1e-15)

@@ -111,3 +111,43 @@ def test_swapped_moment_rows(monkeypatch, Q):
     M[[10, 12]] = M[[12, 10]]
     monkeypatch.setattr(lat, "M", M)
     assert caught(Q)
+
+
+def _totals_pin_caught():
+    import tests.test_oracle_diagnostics as d
+    try:
+        for Q in (19, 27):
+            d.test_totals_of_a_uniform_moving_state_closed_form(Q)
+    except AssertionError:
+        return True
+    return False
+
+
+def test_clean_totals_pass_their_pin():
+    assert not _totals_pin_caught()
+
+
+@pytest.mark.parametrize("mistake", ["no_half_in_kinetic_energy", "momentum_without_half_force",
+                                     "swapped_momentum_components"])
+def test_planted_mistakes_in_totals(monkeypatch, mistake):
+    """The closed-form pin of the totals catches a dropped 1/2 in E_k, momentum summed
+    without the F/2 shift and two momentum components swapped."""
+    orig_moments = lbm.moments
+
+    def bad_moments(f, P, solid=None):
+        rho, u, p, mac = orig_moments(f, P, solid)
+        if mistake == "momentum_without_half_force":
+            u = u - 0.5 * mac["F"] / rho
+        elif mistake == "swapped_momentum_components":
+            u = u[[1, 0, 2]]
+        return rho, u, p, mac
+    monkeypatch.setattr(lbm, "moments", bad_moments)
+    if mistake == "no_half_in_kinetic_energy":
+        orig_totals = lbm.totals
+
+        def bad_totals(f, P, solid=None):
+            t = orig_totals(f, P, solid)
+            t[4] = 2.0 * t[4]
+            return t
+        monkeypatch.setattr(lbm, "totals", bad_totals)
+    assert _totals_pin_caught()
