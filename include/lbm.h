@@ -153,6 +153,24 @@ int64_t lbm_steps_done(const lbm_ctx* c);
    read 0. Synchronous.                                                                 */
 lbm_status lbm_moments(lbm_ctx* c, double* rho, double* u, double* p, double* totals);
 
+/* Totals without allocation, for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the five
+   float64 totals of lbm_moments (sums over fluid nodes of rho, rho u_x, rho u_y, rho u_z
+   and rho |u|^2 / 2, with u of Eq. (10)) written to totals_dev, a caller-owned DEVICE
+   array of 5 doubles. Enqueued on the context stream; returns without waiting (order a
+   read of totals_dev after the stream). Allocates nothing and copies nothing to the host:
+   the partial sums of its reduction go to a fixed device scratch array of the library
+   (1024 blocks x 5 doubles = 40 KiB per device, set up by the first lbm_create on that
+   device and held until the process ends); the reduction runs at most 1024 blocks that
+   stride over the lattice, so every lattice size fits. The summation tree differs from
+   lbm_moments (rounding-level differences; fixed, so repeated calls agree bitwise).
+   Every call on a device overwrites that device's scratch: calls that overlap on one
+   device (different streams, not ordered by events) race and may return wrong totals.
+   The psi buffer of the context is rewritten, as lbm_moments does.
+   Errors: LBM_EINVAL for NULL arguments, LBM_ESTATE before initialisation, LBM_EDEVICE if
+   the scratch of the device was not set up.                                            */
+lbm_status lbm_totals_noalloc(lbm_ctx* c, double* totals_dev);
+
 /* Liquid-phase diagnostics of the current state, reduced on the device: the spreading
    diameter of the film on a wall (Sec. IV A, from the liquid area of the first fluid
    layer), the contact time (Sec. IV B, the droplet has left the solid when no liquid node

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -17,6 +18,34 @@
 #include "misc_kernels.h"
 
 thread_local std::string g_create_error;   // per calling thread
+
+// ---------------------------------------------------------------------------------------
+// Device scratch of lbm_totals_noalloc: the per-block partial sums of its reduction,
+// kTotalsBlocks blocks x 5 doubles = 40 KiB in every device's copy of the library, held
+// until the process ends. Host code never passes the array's name to a kernel (on the host
+// it is only a stand-in for the symbol): the address of each device's copy is looked up
+// once per device, with that device current, when the first lattice is created on it
+// (ensure_scratch, called from lbm_create), and kept in g_scratch_ptr.
+constexpr int kTotalsBlocks = 1024;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kTotalsBlocks * 5];
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+static hipError_t ensure_scratch(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_scratch_ptr[device] = static_cast<double*>(ptr);
+    return e;
+}
+
+static double* scratch_of(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+}
 
 static int default_fused_cfg(const lbm_ctx* c) {
     return fused_cfg_for(c->p.nx, (int)c->elem, c->Q, c->addr64);
@@ -311,6 +340,11 @@ extern "C" lbm_status lbm_create(const lbm_params* pp, lbm_ctx** out) {
     }
     CHK(hipGetDevice(&c->device));
     CHK(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    if (c->device >= kMaxDevices) {
+        fail(c, LBM_EINVAL, "device index %d above %d", c->device, kMaxDevices - 1);
+        return bail(LBM_EINVAL);
+    }
+    CHK(ensure_scratch(c->device));
     if (pp->stream) c->stream = (hipStream_t)pp->stream;
     else { CHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)); c->own_stream = true; }
     const size_t fbytes = (size_t)c->Q * c->stride * c->elem;
@@ -680,6 +714,34 @@ extern "C" lbm_status lbm_moments(lbm_ctx* c, double* rho, double* u, double* p,
     lbm_status st = dispatch<MomentsFn>(c, rho, u, p, totals);
     if (st != LBM_OK) return st;
     return poll_health(c, true);
+}
+
+// The five totals of lbm_moments into a caller-owned device array, with the per-block
+// partial sums in the device scratch (no allocation, no synchronisation).
+template <int Q, typename T>
+struct TotalsNoAllocFn {
+    static lbm_status run(lbm_ctx* c, double* scratch_ptr, double* totals_dev) {
+        using R = typename Arith<T>::type;
+        const long long blocks = std::min<long long>(kTotalsBlocks, (c->N + 255) / 256);
+        StepOps<Q, T>::psi(c, c->f[c->cur]);
+        hipLaunchKernelGGL((k_totals<Q, T>), dim3((unsigned)blocks), dim3(256), 0, c->stream,
+                           (const T*)c->f[c->cur], (const R*)c->psi, scratch_ptr, grid_of(c),
+                           phys_of<R>(c));
+        hipLaunchKernelGGL(k_sum_rows<5>, dim3(1), dim3(256), 0, c->stream, scratch_ptr, blocks,
+                           totals_dev);
+        HIPCHK(c, hipGetLastError());
+        return LBM_OK;
+    }
+};
+
+extern "C" lbm_status lbm_totals_noalloc(lbm_ctx* c, double* totals_dev) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    if (!totals_dev) return fail(c, LBM_EINVAL, "null totals_dev");
+    if (!c->initialised) return fail(c, LBM_ESTATE, "populations not initialised");
+    HIPCHK(c, hipSetDevice(c->device));
+    double* ptr = scratch_of(c->device);
+    if (!ptr) return fail(c, LBM_EDEVICE, "device scratch of device %d not set up", c->device);
+    return dispatch<TotalsNoAllocFn>(c, ptr, totals_dev);
 }
 
 template <int Q, typename T>

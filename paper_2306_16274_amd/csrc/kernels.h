@@ -62,6 +62,57 @@ __global__ __launch_bounds__(256) void k_collide(const T* __restrict__ fin, T* _
     for (int i = 0; i < Q; ++i) store_as<T, R>(fout + (long long)i * g.stride + n, d[i]);
 }
 
+// Macroscopic quantities of one fluid node (x, y, z) at the current time, in float64:
+// rho, j = sum f e + F/2 (Eq. (10)) and u = j / rho; needs psi of the node's neighbourhood.
+struct NodeMoments { double rho, jx, jy, jz, ux, uy, uz; };
+template <int Q, typename T>
+__device__ __forceinline__ NodeMoments node_moments(const T* __restrict__ fin,
+                                                    const typename Arith<T>::type* __restrict__ psi,
+                                                    const Grid& g, const Phys<typename Arith<T>::type>& P,
+                                                    int x, int y, int z, int n) {
+    using R = typename Arith<T>::type;
+    int nb[Q];
+    neighbour_index<Q>(g, x, y, z, nb);
+    R pn[Q];
+    bool snb[Q];
+#pragma unroll
+    for (int j = 1; j < Q; ++j) { pn[j] = psi[nb[j]]; snb[j] = pn[j] < R(0); }
+    pn[0] = psi[n]; snb[0] = false;
+    R d[Q];
+    gather<Q, T, R>(fin, g.stride, n, nb, snb, d);
+    const NodeForce<R> nf = node_force<Q, R>(pn[0], pn, P);
+    const Raw<R> k = forward<Q, R>(d);
+    NodeMoments m;
+    m.rho = (double)P.rho_ref + (double)k.k000;
+    m.jx = (double)k.k100 + 0.5 * (double)nf.Fx;
+    m.jy = (double)k.k010 + 0.5 * (double)nf.Fy;
+    m.jz = (double)k.k001 + 0.5 * (double)nf.Fz;
+    m.ux = m.jx / m.rho; m.uy = m.jy / m.rho; m.uz = m.jz / m.rho;
+    return m;
+}
+
+// Sum of acc[0..C-1] over a 256-thread block (wavefront shuffles, then one value per
+// wavefront through LDS, in a fixed order); thread 0..C-1 writes out[c].
+template <int C>
+__device__ __forceinline__ void block_sums_to(double* acc, double* __restrict__ out) {
+    __shared__ double red[C][8];
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        double v = acc[c];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) red[c][wave] = v;
+    }
+    __syncthreads();
+    if (tid < C) {
+        const int nw = (blockDim.x * blockDim.y + 63) / 64;
+        double s = 0;
+        for (int w = 0; w < nw; ++w) s += red[tid][w];
+        out[tid] = s;
+    }
+}
+
 // Macroscopic fields at the current time: rho, u (with F/2), p = rho/3 + G psi^2/2, and
 // per-block partial sums of rho, rho u, rho |u|^2 / 2 for the totals.
 template <int Q, typename T>
@@ -85,48 +136,42 @@ __global__ __launch_bounds__(256) void k_moments(const T* __restrict__ fin,
             rho_out[n] = 0; p_out[n] = 0;
             u_out[n] = 0; u_out[N + n] = 0; u_out[2 * N + n] = 0;
         } else {
-            int nb[Q];
-            neighbour_index<Q>(g, x, y, z, nb);
-            R pn[Q];
-            bool snb[Q];
-#pragma unroll
-            for (int j = 1; j < Q; ++j) { pn[j] = psi[nb[j]]; snb[j] = pn[j] < R(0); }
-            pn[0] = psi0; snb[0] = false;
-            R d[Q];
-            gather<Q, T, R>(fin, g.stride, n, nb, snb, d);
-            const NodeForce<R> nf = node_force<Q, R>(psi0, pn, P);
-            const Raw<R> k = forward<Q, R>(d);
-            const double rho = (double)P.rho_ref + (double)k.k000;
-            const double jx = (double)k.k100 + 0.5 * (double)nf.Fx;
-            const double jy = (double)k.k010 + 0.5 * (double)nf.Fy;
-            const double jz = (double)k.k001 + 0.5 * (double)nf.Fz;
-            const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
-            rho_out[n] = rho;
-            u_out[n] = ux; u_out[N + n] = uy; u_out[2 * N + n] = uz;
+            const NodeMoments m = node_moments<Q, T>(fin, psi, g, P, x, y, z, n);
+            rho_out[n] = m.rho;
+            u_out[n] = m.ux; u_out[N + n] = m.uy; u_out[2 * N + n] = m.uz;
             const double ps = (double)psi0;
-            p_out[n] = rho / 3.0 + 0.5 * (double)P.G * ps * ps;
-            acc[0] = rho; acc[1] = jx; acc[2] = jy; acc[3] = jz;
-            acc[4] = 0.5 * (jx * ux + jy * uy + jz * uz);
+            p_out[n] = m.rho / 3.0 + 0.5 * (double)P.G * ps * ps;
+            acc[0] = m.rho; acc[1] = m.jx; acc[2] = m.jy; acc[3] = m.jz;
+            acc[4] = 0.5 * (m.jx * m.ux + m.jy * m.uy + m.jz * m.uz);
         }
     }
-    // block reduction: wavefront shuffles, then one value per wavefront through LDS
-    __shared__ double red[5][8];
-    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
-    const int lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-        double v = acc[c];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-        if (lane == 0) red[c][wave] = v;
+    const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+    block_sums_to<5>(acc, partial + b * 5);
+}
+
+// Per-block partial sums of the five totals of k_moments (rho, rho u, rho |u|^2 / 2 over
+// fluid nodes) with no field output: a 1-D grid of gridDim.x blocks of 256 threads that
+// strides over the nodes in index order, so any lattice fits a fixed number of partials
+// (partial[5 b .. 5 b + 4] for block b).
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_totals(const T* __restrict__ fin,
+                                                const typename Arith<T>::type* __restrict__ psi,
+                                                double* __restrict__ partial, Grid g,
+                                                Phys<typename Arith<T>::type> P) {
+    using R = typename Arith<T>::type;
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    const long long nxy = (long long)g.nx * g.ny;
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (long long)gridDim.x * blockDim.x) {
+        if (psi[n] < R(0)) continue;
+        const int z = (int)(n / nxy), r = (int)(n - (long long)z * nxy);
+        const int y = r / g.nx, x = r - y * g.nx;
+        const NodeMoments m = node_moments<Q, T>(fin, psi, g, P, x, y, z, (int)n);
+        acc[0] += m.rho; acc[1] += m.jx; acc[2] += m.jy; acc[3] += m.jz;
+        acc[4] += 0.5 * (m.jx * m.ux + m.jy * m.uy + m.jz * m.uz);
     }
-    __syncthreads();
-    if (tid < 5) {
-        const int nw = (blockDim.x * blockDim.y + 63) / 64;
-        double s = 0;
-        for (int w = 0; w < nw; ++w) s += red[tid][w];
-        const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
-        partial[b * 5 + tid] = s;
-    }
+    block_sums_to<5>(acc, partial + (long long)blockIdx.x * 5);
 }
 
 // Store f_bar(x) (float64, Q planes of N) into the pull layout: population i of node x

@@ -82,6 +82,7 @@ _SIGS = {
     "lbm_steps_done": (ctypes.c_int64, [_P]),
     "lbm_moments": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "lbm_liquid_stats": (ctypes.c_int, [_P, _D, _D, _D, ctypes.c_int32, _P, _P, _P]),
+    "lbm_totals_noalloc": (ctypes.c_int, [_P, _P]),
     "lbm_synchronize": (ctypes.c_int, [_P]),
     "lbm_copy_bandwidth": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(_D)]),
     "lbm_kernel_times": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, ctypes.c_int32, _P]),
@@ -191,6 +192,11 @@ def lbm_moments(ctx, shape, want=("rho", "u", "p", "totals")):
         if v is not None:
             out[k] = v
     return out
+
+
+def lbm_totals_noalloc(ctx, totals_dev_ptr):
+    """Enqueue the five totals into a device array of 5 float64 (address as an int)."""
+    _check(library().lbm_totals_noalloc(ctx, ctypes.c_void_p(int(totals_dev_ptr))), ctx)
 
 
 def lbm_liquid_stats(ctx, nz, threshold, rho_v, rho_l, reach=1):
