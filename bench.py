@@ -3,12 +3,14 @@
 One step is one time step of the whole hot path (streaming with bounce-back, density and
 pseudopotential, interaction / wetting / surface-tension terms, moment-space collision,
 back-transform, store) over the lattice of the workload. The workload is a 256^3 D3Q19
-static droplet (Carnahan-Starling EOS at T = 0.5 T_c, paper relaxation rates, +-1 %
-interface noise), populations resident in HBM before timing starts.
+static droplet (Carnahan-Starling EOS at T = 0.5 T_c, all non-viscous relaxation rates 1,
+nu = 0.1, +-1 % interface noise), populations resident in HBM before timing starts.
 
 Prints one JSON line (rank 0): the FP32 shifted-storage throughput in MLUPS as `value`,
 the FP64 and FP16-shifted throughputs beside it, the HBM roofline of the dominant kernel
-measured with HIP events on the launch stream, and the CPU oracle timed on a bounded sample.
+measured with HIP events on the launch stream, a time-compressed serving sweep (p50/p99
+time to result and aggregate MLUPS of continuous batching against one-at-a-time plain
+launches) and the CPU oracle timed on a bounded sample (one core and all cores).
 """
 import argparse
 import hashlib
@@ -127,23 +129,27 @@ def copy_bandwidth(nbytes=2 << 30, reps=10):
     return gbs
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """The FP64 CPU oracle on a bounded sample of the workload: a 64^3 box with the same
-    physics (droplet radius scaled by 1/4), single thread."""
-    from threadpoolctl import threadpool_limits
-    import synth_inputs as si
+def _oracle_sample(w, n):
+    import synth_inputs as si  # noqa: F401
     from oracle import lbm as olbm
     from tests.helpers import maxwell, oracle_params
-    n = 64
-    ws = w.with_(nx=n, ny=n, nz=n, R=w.R / 4.0)
+    ws = w.with_(nx=n, ny=n, nz=n, R=w.R * n / w.nx)
+    rv, rl = maxwell(ws)
+    P = oracle_params(ws)
+    cx, cy, cz = ws.droplet_centre()
+    rho, u = olbm.droplet_fields(P, cx, cy, cz, ws.R, ws.W, rl, rv, noise_amp=ws.noise,
+                                 seed=ws.seed)
+    return ws, P, olbm.equilibrium_populations(P, rho, u), olbm.solid_mask(P)
+
+
+def _oracle_run(args):
+    """One process of the CPU baseline: FP64 oracle steps on the sample for budget_s
+    seconds, one thread; returns (node updates, seconds)."""
+    w, n, budget_s = args
+    from threadpoolctl import threadpool_limits
+    from oracle import lbm as olbm
     with threadpool_limits(limits=1):
-        rv, rl = maxwell(ws)
-        P = oracle_params(ws)
-        cx, cy, cz = ws.droplet_centre()
-        rho, u = olbm.droplet_fields(P, cx, cy, cz, ws.R, ws.W, rl, rv, noise_amp=ws.noise,
-                                     seed=ws.seed)
-        f = olbm.equilibrium_populations(P, rho, u)
-        solid = olbm.solid_mask(P)
+        ws, P, f, solid = _oracle_sample(w, n)
         f = olbm.step(f, P, solid)          # warm-up
         steps, t = 0, 0.0
         t0 = time.perf_counter()
@@ -151,9 +157,76 @@ def cpu_baseline(w, budget_s=15.0):
             f = olbm.step(f, P, solid)
             steps += 1
             t = time.perf_counter() - t0
-    return dict(value=ws.nodes * steps / t / 1e6, unit="MLUPS", cores=1, kind="oracle",
-                sample=f"{n}^3 D3Q19 box of the same workload (droplet R={ws.R:g}), "
-                       f"{steps} FP64 numpy steps in {t:.1f} s, one thread")
+    return ws.nodes * steps, t
+
+
+def host_cpu():
+    """CPU model name and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return model, cores
+
+
+def cpu_baseline(w, budget_s=10.0, n=64, max_procs=16):
+    """The FP64 CPU oracle on a bounded sample of the workload (a 64^3 box with the same
+    physics, droplet radius scaled by 1/4): one process on one thread, then one process per
+    usable core (at most max_procs) on independent copies of the sample at once."""
+    from concurrent.futures import ProcessPoolExecutor
+    model, cores = host_cpu()
+    lups, t = _oracle_run((w, n, budget_s))
+    single = lups / t / 1e6
+    procs = max(1, min(cores, max_procs))
+    with ProcessPoolExecutor(max_workers=procs) as ex:
+        res = list(ex.map(_oracle_run, [(w, n, budget_s)] * procs))
+    all_cores = sum(l for l, _ in res) / max(tt for _, tt in res) / 1e6
+    return dict(value=single, unit="MLUPS", cores=1, kind="oracle",
+                sample=f"{n}^3 D3Q19 box of the same workload (droplet R={w.R * n / w.nx:g}), "
+                       f"FP64 numpy oracle steps for {budget_s:g} s, one thread",
+                all_cores={"value": all_cores, "unit": "MLUPS", "cores": procs,
+                           "sample": f"{procs} processes, one thread each, each on its own "
+                                     f"copy of the sample for {budget_s:g} s"},
+                cpu_model=model, host_cores=cores)
+
+
+def serving_sweep(n_requests, seed=2306):
+    """Time-compressed serving sweep: the serving trace's distribution (cubic boxes
+    log-uniform in [64, 192], contact angle, impact speed, droplet R = L/6) with step counts
+    and arrival gaps divided by ten (200-800 steps, Poisson arrivals at 40 per second: the
+    same offered load in node updates per second), served by continuous batching in FP32
+    shifted storage and, as baselines, one request at a time with plain launches in FP64
+    (the survey's baseline) and in FP32 (the same bytes per node as the batched loop)."""
+    import torch
+    import synth_inputs as si
+    from paper_2306_16274_amd import serving
+    trace = si.serving_trace(n_requests, rate_per_s=40.0, seed=seed, steps_lo=200,
+                             steps_hi=800)
+    stream = torch.cuda.Stream()
+    out = {"requests": n_requests, "trace": "serving trace / 10: steps 200-800, 40 arrivals/s, "
+                                           f"L log-uniform in [64, 192], seed {seed}"}
+    for spec in ("batched:fp32", "sequential:fp64", "sequential:fp32"):
+        mode, storage = spec.split(":")
+        r = serving.serve(trace, mode, storage, chunk=50, stream=stream.cuda_stream)
+        out[spec] = {"p50_s": round(r["p50_s"], 3), "p99_s": round(r["p99_s"], 3),
+                     "aggregate_MLUPS": round(r["aggregate_mlups"], 1),
+                     "makespan_s": round(r["makespan_s"], 2), "failed": r["failed"]}
+    b = out["batched:fp32"]
+    for base in ("sequential:fp64", "sequential:fp32"):
+        o = out[base]
+        out["gain_vs_" + base.replace(":", "_")] = {
+            "aggregate": round(b["aggregate_MLUPS"] / o["aggregate_MLUPS"], 3),
+            "p99": round(o["p99_s"] / b["p99_s"], 3)}
+    return out
 
 
 def main():
@@ -166,6 +239,8 @@ def main():
     ap.add_argument("--slab-steps", type=int, default=200,
                     help="steps on one GPU's z-slab of the workload shared by 8 GPUs (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=64,
+                    help="requests of the time-compressed serving sweep (0: skip)")
     ap.add_argument("--rho-ref", default="vapour", choices=["zero", "vapour", "liquid"])
     ap.add_argument("--step-kernel", default="fused", choices=["fused", "two_pass"])
     args = ap.parse_args()
@@ -175,14 +250,18 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
     import synth_inputs as si
+    w = si.LAPLACE_256
+    # the CPU oracle first, before this process touches the GPU (its worker processes are
+    # forked from a process without a HIP runtime)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(w)
+
+    import torch
     from paper_2306_16274_amd import lbm as L
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    w = si.LAPLACE_256
     Q = w.Q
 
     r32 = run_gpu(w, "fp32", args.steps, args.warmup, args.rho_ref, args.step_kernel)
@@ -198,6 +277,7 @@ def main():
                 "us_per_step": round(1000 * rs["ms_per_step"], 1),
                 "kernel_us": round(1000 * max(rs["kernel_ms"].values()), 1),
                 "steps": args.slab_steps, "storage": "fp32 shifted"}
+    serving_block = serving_sweep(args.serving_requests) if args.serving_requests > 0 else None
     copy_gbs = copy_bandwidth()
     stream_copy_gbs = L.lbm_copy_bandwidth()
 
@@ -257,7 +337,8 @@ def main():
                      "alg_bytes_per_node": per_node, "alg_bytes_per_launch": alg_bytes,
                      "kernel_ms": round(kms, 5),
                      "frac_of_copy": round(achieved / stream_copy_gbs, 4)},
-        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(w),
+        "serving": serving_block,
+        "cpu_baseline": cpu,
         "mass": r32["mass"],
     }
     out["source_hash"] = kernel_source_hash()

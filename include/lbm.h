@@ -201,6 +201,14 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int64_t nsteps, double* avg_ms, const ch
    times `reps` copies with HIP events on a private stream. Synchronous.                 */
 lbm_status lbm_copy_bandwidth(int64_t bytes, int32_t reps, double* gbs);
 
+/* Result of the periodic health checks (reduce_every, and the checks after lbm_batch_run)
+   without enqueueing anything: LBM_ENONFINITE if a completed check found a non-finite or
+   non-positive density (now or earlier; the context then refuses further steps), else
+   LBM_OK. wait = 0 does not block (a check still in flight counts as passed for now);
+   wait != 0 waits for the last check enqueued. For a serving loop that evicts failed
+   lattices without draining the device.                                                */
+lbm_status lbm_health_status(lbm_ctx* c, int32_t wait);
+
 /* Wait for all work enqueued on the context stream.                                   */
 lbm_status lbm_synchronize(lbm_ctx* c);
 

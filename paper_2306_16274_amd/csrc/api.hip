@@ -541,6 +541,13 @@ extern "C" lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
     return run_steps(c, nsteps, nullptr);
 }
 
+extern "C" lbm_status lbm_health_status(lbm_ctx* c, int32_t wait) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "null context");
+    if (c->failed) return fail(c, LBM_ENONFINITE, "a previous health check failed");
+    HIPCHK(c, hipSetDevice(c->device));
+    return poll_health(c, wait != 0);
+}
+
 extern "C" lbm_status lbm_kernel_times(lbm_ctx* c, int64_t nsteps, double* avg_ms,
                                        const char** names, int32_t cap, int32_t* count) {
     if (!c || !avg_ms || !count || cap < 1) return fail(c, LBM_EINVAL, "null argument");

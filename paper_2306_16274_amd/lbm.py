@@ -84,6 +84,7 @@ _SIGS = {
     "lbm_liquid_stats": (ctypes.c_int, [_P, _D, _D, _D, ctypes.c_int32, _P, _P, _P]),
     "lbm_totals_noalloc": (ctypes.c_int, [_P, _P]),
     "lbm_synchronize": (ctypes.c_int, [_P]),
+    "lbm_health_status": (ctypes.c_int, [_P, ctypes.c_int32]),
     "lbm_copy_bandwidth": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(_D)]),
     "lbm_kernel_times": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, ctypes.c_int32, _P]),
     "lbm_coexistence": (ctypes.c_int, [ctypes.POINTER(lbm_params), ctypes.POINTER(_D),
@@ -228,6 +229,14 @@ def lbm_kernel_times(ctx, nsteps, cap=8):
 
 def lbm_synchronize(ctx):
     _check(library().lbm_synchronize(ctx), ctx)
+
+
+def lbm_health_status(ctx, wait=False):
+    """LBM_OK or LBM_ENONFINITE (returned, not raised): the last completed health check."""
+    st = library().lbm_health_status(ctx, 1 if wait else 0)
+    if st not in (LBM_OK, LBM_ENONFINITE):
+        _check(st, ctx)
+    return st
 
 
 def lbm_coexistence(params):

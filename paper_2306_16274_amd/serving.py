@@ -46,6 +46,9 @@ def g_ads_for_angle(theta_deg):
 _COEX = {}
 
 
+HEALTH_EVERY = 200         # steps between health checks of a request's lattice
+
+
 def request_params(req, storage="fp32"):
     p = L.lbm_params_default()
     p.lattice = 19
@@ -56,6 +59,7 @@ def request_params(req, storage="fp32"):
     p.sigma, p.kappa = 0.1, 0.0
     p.G_ads = g_ads_for_angle(req["theta"])
     p.bc[2][0] = p.bc[2][1] = L.LBM_BC_WALL
+    p.reduce_every = HEALTH_EVERY
     key = (p.eos, p.T_over_Tc, p.cs_a, p.cs_b, p.cs_R)
     if key not in _COEX:
         _COEX[key] = L.lbm_coexistence(p)
@@ -102,7 +106,11 @@ def start_job(req, storage, stream, t_now):
 def finish_job(job):
     """Read the result of a finished request, reduced on the device: the spreading diameter
     (diameter of the equal-area disc of the liquid nodes in the first fluid layer, z = 1,
-    Sec. IV A), the liquid volume and the total mass."""
+    Sec. IV A), the liquid volume and the total mass. A lattice whose last health check
+    failed (detected only now: the check was still in flight at the chunk boundaries) gives
+    the record of an evicted request."""
+    if L.lbm_health_status(job.lat.ctx, wait=True) == L.LBM_ENONFINITE:
+        return evicted_result(job)
     thr = 0.5 * (job.rho_l + job.rho_v)
     counts, _, volume = job.lat.liquid_stats(thr, job.rho_v, job.rho_l)
     d_f = 2.0 * math.sqrt(float(counts[1]) / math.pi)
@@ -110,6 +118,14 @@ def finish_job(job):
     job.lat.close()
     return dict(spread_diameter=d_f, spread_ratio=d_f / float(job.req["R"]), mass=mass,
                 liquid_volume=volume, finite=bool(np.isfinite(mass)))
+
+
+def evicted_result(job):
+    """Result record of a request whose lattice failed its health check (non-finite or
+    non-positive density): it is dropped from the batch and its lattice freed."""
+    job.lat.close()
+    return dict(spread_diameter=float("nan"), spread_ratio=float("nan"), mass=float("nan"),
+                liquid_volume=float("nan"), finite=False)
 
 
 def serve(trace, mode="batched", storage="fp32", budget_bytes=64 << 30, max_slots=64,
@@ -122,6 +138,9 @@ def serve(trace, mode="batched", storage="fp32", budget_bytes=64 << 30, max_slot
     256-request sweep, 16 Mi nodes keep 98 % of the throughput of 48 Mi and cut p50 / p99
     from 62-76 / 78-101 s to 53 / 76 s).
     phases: optional dict that accumulates host seconds per loop phase.
+    A request whose lattice fails its periodic health check (every HEALTH_EVERY steps) is
+    evicted at the next chunk boundary: it leaves the batch, its lattice is freed and its
+    record says finite = False.
     Returns a dict with per-request records and the aggregate figures."""
     clock = time.perf_counter
     if phases is None:
@@ -140,6 +159,7 @@ def serve(trace, mode="batched", storage="fp32", budget_bytes=64 << 30, max_slot
     def now():
         return (time.perf_counter() - t0) * time_scale
 
+    evicted = []           # failed lattices, closed once no batch refers to them
     retiring = []          # finished in the previous chunk; results read after the next enqueue
     futures = []           # (job, future) of result readbacks in flight
     pool = ThreadPoolExecutor(max_workers=2)
@@ -147,6 +167,13 @@ def serve(trace, mode="batched", storage="fp32", budget_bytes=64 << 30, max_slot
     def retire(j):
         res = finish_job(j)
         return res, now()
+
+    def record(j, res, t_done):
+        rec = dict(id=j.req["id"], L=j.req["L"], steps=j.steps, t_arrival=j.req["t_arrival"],
+                   t_admit=j.t_admit, t_done=t_done, latency=t_done - j.req["t_arrival"], **res)
+        records.append(rec)
+        if log:
+            log(rec)
 
     def collect(block):
         nonlocal used
@@ -157,12 +184,7 @@ def serve(trace, mode="batched", storage="fp32", budget_bytes=64 << 30, max_slot
             ts = clock()
             res, t_done = fut.result()
             tick("retire", ts)
-            rec = dict(id=j.req["id"], L=j.req["L"], steps=j.steps, t_arrival=j.req["t_arrival"],
-                       t_admit=j.t_admit, t_done=t_done,
-                       latency=t_done - j.req["t_arrival"], **res)
-            records.append(rec)
-            if log:
-                log(rec)
+            record(j, res, t_done)
             used -= j.footprint
             futures.remove(item)
     inflight = []          # events after the last chunks, to keep at most 2 chunks queued
@@ -219,15 +241,34 @@ def serve(trace, mode="batched", storage="fp32", budget_bytes=64 << 30, max_slot
                     ts = clock()
                     L.lbm_batch_destroy(old)
                     tick("rebuild", ts)
+                    for j in evicted:       # no batch refers to them any more
+                        record(j, evicted_result(j), now())
+                        used -= j.footprint
+                    evicted = []
+                failed = [j for j in active
+                          if L.lbm_health_status(j.lat.ctx) == L.LBM_ENONFINITE]
             else:
                 ts = clock()
+                failed = []
                 for j in active:
                     j.lat.step(k)
-                    j.lat.synchronize()
+                    try:
+                        j.lat.synchronize()
+                    except L.LbmError as err:
+                        if err.status != L.LBM_ENONFINITE:
+                            raise
+                        failed.append(j)
                 tick("enqueue", ts)
             for j in active:
                 j.done_steps += k
                 work += float(j.req["L"]) ** 3 * k
+            for j in failed:           # evicted: leaves the batch at the next rebuild
+                active.remove(j)
+                if mode == "batched":
+                    evicted.append(j)
+                else:
+                    record(j, evicted_result(j), now())
+                    used -= j.footprint
             finished = [j for j in active if j.remaining == 0]
             for j in finished:
                 active.remove(j)
@@ -250,9 +291,12 @@ def serve(trace, mode="batched", storage="fp32", budget_bytes=64 << 30, max_slot
     pool.shutdown()
     if batch is not None:
         L.lbm_batch_destroy(batch)
+    for j in evicted:
+        record(j, evicted_result(j), now())
     makespan = now() - min(r["t_arrival"] for r in trace) if trace else 0.0
     lat = np.array([r["latency"] for r in records])
-    return dict(mode=mode, storage=storage, requests=len(records), phases_s=phases,
+    return dict(mode=mode, storage=storage, requests=len(records),
+                failed=sum(1 for r in records if not r["finite"]), phases_s=phases,
                 makespan_s=makespan / time_scale,
                 aggregate_mlups=work / (makespan / time_scale) / 1e6 if makespan > 0 else 0.0,
                 p50_s=float(np.percentile(lat, 50)) / time_scale if len(lat) else None,

@@ -159,3 +159,68 @@ def test_batch_members_match_the_oracle(L, storage):
         assert er < (1e-12 if storage == "fp64" else 1e-5), w.name
         assert eu < (1e-13 if storage == "fp64" else 1e-4), w.name
         lat.close()
+
+
+def test_batched_fp32_matches_sequential_fp64(L):
+    """Equal accuracy of the two serving modes: three requests of the serving workload
+    (CS at 0.7 T_c, walls, wetting, a falling droplet; boxes 40-72) advanced 200 steps in
+    one FP32 shifted-storage batch and, one at a time, in FP64 with plain launches: every
+    fluid node's rho within 1e-5 relative and u within 1e-4 absolute (the FP32 tolerances
+    against FP64)."""
+    from paper_2306_16274_amd import serving
+    trace = si.serving_trace(3, seed=11, L_lo=40, L_hi=72, steps_lo=200, steps_hi=200)
+    b32 = [serving.start_job(r, "fp32", None, 0.0) for r in trace]
+    b = L.lbm_batch_create([j.lat.ctx for j in b32], serving.STEP_QUANTUM)
+    try:
+        L.lbm_batch_run(b, 200 // serving.STEP_QUANTUM)
+    finally:
+        L.lbm_batch_destroy(b)
+    for r, j32 in zip(trace, b32):
+        j64 = serving.start_job(r, "fp64", None, 0.0)
+        j64.lat.step(200)
+        m64 = j64.lat.moments(want=("rho", "u"))
+        m32 = j32.lat.moments(want=("rho", "u"))
+        fl = m64["rho"] > 0
+        er = float(np.max(np.abs(m32["rho"][fl] - m64["rho"][fl]) / m64["rho"][fl]))
+        eu = float(np.max(np.abs(m32["u"][:, fl] - m64["u"][:, fl])))
+        print(f"request L={r['L']} theta={r['theta']:.0f}: batched fp32 vs fp64 rho {er:.2e} "
+              f"u {eu:.2e}")
+        assert er < 1e-5 and eu < 1e-4, (r["L"], er, eu)
+        j64.lat.close()
+        j32.lat.close()
+
+
+@pytest.mark.parametrize("mode", ["batched", "sequential"])
+def test_serving_evicts_a_failed_request(L, monkeypatch, mode):
+    """A request whose lattice goes non-finite (a NaN planted in its populations right
+    after it is created) is evicted by the serving loop at the next health check: its record
+    says finite = False, every other request finishes with exactly the result of a clean
+    run of the same trace."""
+    import torch
+    from paper_2306_16274_amd import serving
+    monkeypatch.setattr(serving, "HEALTH_EVERY", 20)
+    trace = si.serving_trace(6, rate_per_s=40.0, seed=5, L_lo=24, L_hi=40, steps_lo=60,
+                             steps_hi=120)
+    stream = torch.cuda.Stream()
+    clean = serving.serve(trace, mode, "fp32", chunk=20, stream=stream.cuda_stream)
+    start = serving.start_job
+
+    def start_with_nan(req, storage, s, t_now):
+        job = start(req, storage, s, t_now)
+        if req["id"] == 2:
+            f = job.lat.get_populations()
+            f[1, 3, 4, 5] = np.nan
+            job.lat.set_populations(f)
+        return job
+    monkeypatch.setattr(serving, "start_job", start_with_nan)
+    bad = serving.serve(trace, mode, "fp32", chunk=20, stream=stream.cuda_stream)
+    assert clean["failed"] == 0 and bad["failed"] == 1
+    by_id = {r["id"]: r for r in clean["records"]}
+    assert len(bad["records"]) == 6
+    for r in bad["records"]:
+        if r["id"] == 2:
+            assert not r["finite"]
+            continue
+        c = by_id[r["id"]]
+        assert r["finite"] and r["mass"] == c["mass"], r["id"]
+        assert r["spread_diameter"] == c["spread_diameter"], r["id"]

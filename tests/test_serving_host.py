@@ -21,6 +21,8 @@ class Recorder:
         self.peak_alive = 0
         self.log = []              # ctx of every step call, in order
         self.peak_batch = 0        # most lattices in one batched launch
+        self.failing = set()       # ctx whose health check reports a non-finite density
+        self.fail_sizes = set()    # box sizes L whose lattices fail
 
 
 def install_fakes(monkeypatch, rec):
@@ -33,6 +35,8 @@ def install_fakes(monkeypatch, rec):
                 FakeLattice._next[0] += 1
                 self.nz = params.nz
                 rec.alive[self.ctx] = L.lbm_footprint_bytes(params)
+                if params.nx in rec.fail_sizes:
+                    rec.failing.add(self.ctx)
                 rec.steps[self.ctx] = 0
                 rec.peak_bytes = max(rec.peak_bytes, sum(rec.alive.values()))
                 rec.peak_alive = max(rec.peak_alive, len(rec.alive))
@@ -46,7 +50,9 @@ def install_fakes(monkeypatch, rec):
                 rec.log.append(self.ctx)
 
         def synchronize(self):
-            pass
+            with rec.lock:
+                if self.ctx in rec.failing:
+                    raise L.LbmError(L.LBM_ENONFINITE, "planted failure")
 
         def liquid_stats(self, thr, rv, rl, reach=1):
             c = np.zeros(self.nz, dtype=np.int64)
@@ -80,6 +86,11 @@ def install_fakes(monkeypatch, rec):
     monkeypatch.setattr(serving.L, "lbm_batch_create", batch_create)
     monkeypatch.setattr(serving.L, "lbm_batch_run", batch_run)
     monkeypatch.setattr(serving.L, "lbm_batch_destroy", lambda b: None)
+
+    def health(ctx, wait=False):
+        with rec.lock:
+            return L.LBM_ENONFINITE if ctx in rec.failing else L.LBM_OK
+    monkeypatch.setattr(serving.L, "lbm_health_status", health)
 
 
 def _trace():
@@ -142,3 +153,26 @@ def test_sequential_loop_runs_one_request_at_a_time_in_arrival_order(monkeypatch
     done = [r["id"] for r in sorted(out["records"], key=lambda r: r["t_done"])]
     assert done == [r["id"] for r in sorted(trace, key=lambda r: r["t_arrival"])]
     assert sorted(rec.closed.values()) == sorted(serving.steps_of(r) for r in trace)
+
+
+@pytest.mark.parametrize("mode", ["batched", "sequential"])
+def test_failed_request_is_evicted_and_freed(monkeypatch, mode):
+    """A lattice whose health check fails is evicted at the next chunk boundary: it is never
+    batched again, its lattice is freed, its record says finite = False, and every other
+    request completes its full step count."""
+    rec = Recorder()
+    install_fakes(monkeypatch, rec)
+    trace = _trace()
+    bad_L = trace[3]["L"]
+    rec.fail_sizes.add(bad_L)
+    out = serving.serve(trace, mode, "fp32", chunk=40)
+    assert out["requests"] == len(trace)
+    bad = [r for r in out["records"] if r["L"] == bad_L]
+    assert bad and all(not r["finite"] for r in bad)
+    assert out["failed"] == len(bad)
+    assert all(r["finite"] for r in out["records"] if r["L"] != bad_L)
+    assert not rec.alive                      # every lattice freed, the failed ones too
+    good = sorted(serving.steps_of(r) for r in trace if r["L"] != bad_L)
+    assert sorted(v for c, v in rec.closed.items() if c not in rec.failing) == good
+    # a failed lattice stops within one chunk of its first check
+    assert all(v <= 2 * 40 for c, v in rec.closed.items() if c in rec.failing)
