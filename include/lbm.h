@@ -49,6 +49,8 @@ enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16 = 2 };       /* population storage t
 enum { LBM_EOS_CS = 0, LBM_EOS_PIECEWISE = 1 };          /* equation of state         */
 enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1 };           /* per domain face           */
 enum { LBM_STEP_FUSED = 0, LBM_STEP_TWO_PASS = 1 };      /* kernel schedule of a step */
+enum { LBM_WALL_PSI_NODE = 0, LBM_WALL_PSI_FLUID_MEAN = 1,  /* psi at solid neighbours   */
+       LBM_WALL_PSI_ZERO = 2, LBM_WALL_PSI_MIRROR = 3 };
 
 /*
  * Problem statement. Defaults (lbm_params_default) follow Sec. II B: s0 = s1 = 1,
@@ -88,10 +90,23 @@ typedef struct {
                                  recomputed on chip (default). LBM_STEP_TWO_PASS: a
                                  density/psi pass, then the collision pass. Same results
                                  up to rounding order.                                    */
+    int32_t wall_psi;         /* psi taken at a solid neighbour in F_int (Eq. (16)) and
+                                 Q_ab (Eq. (B2)), which the paper leaves open:
+                                 LBM_WALL_PSI_NODE (psi of the fluid node itself),
+                                 LBM_WALL_PSI_FLUID_MEAN (sum w_i psi(x+e_i) / sum w_i over
+                                 the fluid neighbours of x), LBM_WALL_PSI_ZERO or
+                                 LBM_WALL_PSI_MIRROR (psi(x + e') with e' = e_i less every
+                                 component along which the axis neighbour of x is solid:
+                                 for a flat wall the mirror image of x + e_i across the
+                                 wall; psi(x) where e' = 0 or x + e' is solid; the
+                                 default: it makes G_ads = 0 neutral, 90 degrees, and
+                                 G_ads = 0.23 give 157 degrees, as Sec. III E states). The
+                                 wetting force of Eq. (22) is added in every case.         */
 } lbm_params;
 
 /* Fill *p with the defaults above (D3Q19, FP32, 64^3, CS EOS at T = 0.7 T_c, a = 0.5,
-   b = 4, R = 1, nu = 0.1, fully periodic, rho_ref = 0). Returns LBM_EINVAL on NULL.    */
+   b = 4, R = 1, nu = 0.1, fully periodic, rho_ref = 0, wall_psi = LBM_WALL_PSI_MIRROR).
+   Returns LBM_EINVAL on NULL.                                                           */
 lbm_status lbm_params_default(lbm_params* p);
 
 /* Validate *p, allocate the lattice on the current HIP device and return a context in

@@ -23,7 +23,13 @@ Readings taken where the paper is silent (each is listed with its reason in the 
 * walls are halfway bounce-back: a population that would stream into a solid node returns
   to its origin in the opposite direction at the next time level; solid nodes carry no
   populations (they are held at 0 here);
-* psi at a solid neighbour, in F_int and Q_ab, is psi of the evaluating fluid node;
+* psi at a solid neighbour, in F_int and Q_ab (not specified by the paper), follows
+  Params.wall_psi: "node" (psi of the evaluating fluid node), "fluid_mean"
+  (the w-weighted mean of psi over the node's fluid neighbours), "zero", or "mirror"
+  (psi at x + e' where e' is e_i without the components along which the axis neighbour
+  of x is solid: for a flat wall the mirror image of x + e_i across the wall; psi of the
+  node where e' = 0 or x + e' is solid; the default: of these readings it alone makes
+  G_ads = 0 neutral and G_ads = 0.23 about 157 degrees, the two statements of Sec. III E);
 * the s_e of Eq. (B1) is the bulk rate s_2b of Eq. (12);
 * |F_int|^2 / psi^2 where psi = 0 is its limit G^2 |sum_i w_i psi(x+e_i) e_i|^2;
 * the kinematic viscosity may vary linearly with rho (Sec. IV A, Eq. (24)); s_nu follows
@@ -65,6 +71,7 @@ class Params:
     walls: dict = field(default_factory=dict)   # {'z_lo': True, 'z_hi': True, ...}
     cylinder: tuple = None            # x-aligned: (y_c, z_c, radius)
     body_force: tuple = (0.0, 0.0, 0.0)
+    wall_psi: str = "mirror"          # psi at solid neighbours: node|fluid_mean|zero|mirror
 
     @property
     def lat(self):
@@ -100,11 +107,61 @@ def neighbour(a, e):
     return np.roll(a, shift=(-int(e[2]), -int(e[1]), -int(e[0])), axis=(0, 1, 2))
 
 
+def mirror_psi(psi, solid, P, e):
+    """psi at the image of the solid neighbour x + e under the "mirror" reading: drop
+    every component of e along which the axis neighbour of x (one step in that component's
+    direction) is solid; psi(x + e') if e' != 0 and x + e' is fluid, else psi(x)."""
+    keep = []
+    for a in range(3):
+        if e[a] == 0:
+            keep.append(np.zeros(psi.shape, dtype=bool))
+        else:
+            step = np.zeros(3, dtype=np.int64)
+            step[a] = e[a]
+            keep.append(~neighbour(solid, step))
+    out = psi.copy()
+    for kx in (0, 1):
+        for ky in (0, 1):
+            for kz in (0, 1):
+                ep = np.array([e[0] * kx, e[1] * ky, e[2] * kz])
+                if not ep.any():
+                    continue
+                sel = ((keep[0] == bool(kx)) & (keep[1] == bool(ky)) & (keep[2] == bool(kz))
+                       & ~neighbour(solid, ep))
+                out = np.where(sel, neighbour(psi, ep), out)
+    return out
+
+
+def wall_psi_values(psi, solid, P):
+    """psi assigned to the solid neighbours of each node (Params.wall_psi): the node's own
+    psi, 0, or sum_i w_i psi(x + e_i) / sum_i w_i over the fluid neighbours x + e_i of x
+    (psi of the node where it has no fluid neighbour). None for the "mirror" reading,
+    whose value depends on the link (mirror_psi)."""
+    if P.wall_psi == "node":
+        return psi
+    if P.wall_psi == "zero":
+        return np.zeros_like(psi)
+    if P.wall_psi == "mirror":
+        return None
+    if P.wall_psi != "fluid_mean":
+        raise ValueError("wall_psi must be node, fluid_mean, zero or mirror")
+    lat = P.lat
+    num = np.zeros(psi.shape)
+    den = np.zeros(psi.shape)
+    for i in range(1, lat.Q):
+        fl = ~neighbour(solid, lat.e[i])
+        num += lat.w[i] * np.where(fl, neighbour(psi, lat.e[i]), 0.0)
+        den += lat.w[i] * fl
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(den > 0, num / np.where(den > 0, den, 1.0), psi)
+
+
 def forces(psi, solid, P):
     """F_int (Eq. (16)), F_ads (Eq. (22)), Q_ab (Eq. (B2)) and |F_int|^2/psi^2 at every node.
 
     Returns (F_int (3,...), F_ads (3,...), Qab dict, phi)."""
     lat = P.lat
+    psi_w = wall_psi_values(psi, solid, P)
     F_int = np.zeros((3,) + psi.shape)
     F_ads = np.zeros((3,) + psi.shape)
     Qab = {k: np.zeros(psi.shape) for k in ("xx", "yy", "zz", "xy", "xz", "yz")}
@@ -113,7 +170,8 @@ def forces(psi, solid, P):
         e = lat.e[i]
         w = lat.w[i]
         nb_solid = neighbour(solid, e)
-        psi_nb = np.where(nb_solid, psi, neighbour(psi, e))
+        pw = psi_w if psi_w is not None else mirror_psi(psi, solid, P, e)
+        psi_nb = np.where(nb_solid, pw, neighbour(psi, e))
         for a in range(3):
             S_int[a] += w * psi_nb * e[a]
             F_ads[a] += -P.G_ads * psi * w * psi * nb_solid * e[a]

@@ -170,6 +170,7 @@ extern "C" lbm_status lbm_params_default(lbm_params* p) {
     p->pw_theta_v = 1.0 / 6.0; p->pw_theta_m = -1.0 / 120.0; p->pw_theta_l = 1.0 / 3.0;
     p->pw_rho1 = 0.0013246030524; p->pw_rho2 = 0.9758004064415;
     p->G = -1.0; p->sigma = 0.1; p->kappa = 0.0; p->G_ads = 0.0;
+    p->wall_psi = LBM_WALL_PSI_MIRROR;
     p->nu_l = p->nu_v = 0.1; p->rho_l = 1.0; p->rho_v = 0.001;
     p->s0 = 1.0; p->s1 = 1.0; p->s2b = 0.6; p->s3 = 1.2; p->s3b = 0.6;
     p->s4 = 1.2; p->s4b = 1.2; p->s5 = 1.2; p->s6 = 1.2;
@@ -207,6 +208,7 @@ static Phys<R> make_phys(const lbm_params& p) {
     P.nu_v = (R)p.nu_v; P.rho_v = (R)p.rho_v;
     P.dnu_drho = P.var_nu ? (R)((p.nu_l - p.nu_v) / (p.rho_l - p.rho_v)) : R(0);
     P.bfx = (R)p.body_force[0]; P.bfy = (R)p.body_force[1]; P.bfz = (R)p.body_force[2];
+    P.wall_psi = p.wall_psi;
     return P;
 }
 
@@ -246,6 +248,8 @@ static lbm_status validate(const lbm_params& p) {
     if (p.reduce_every < 0) return fail(nullptr, LBM_EINVAL, "reduce_every must be >= 0");
     if (p.step_kernel != LBM_STEP_FUSED && p.step_kernel != LBM_STEP_TWO_PASS)
         return fail(nullptr, LBM_EINVAL, "unknown step_kernel");
+    if (p.wall_psi < LBM_WALL_PSI_NODE || p.wall_psi > LBM_WALL_PSI_MIRROR)
+        return fail(nullptr, LBM_EINVAL, "unknown wall_psi");
     return LBM_OK;
 }
 

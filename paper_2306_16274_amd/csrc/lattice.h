@@ -60,6 +60,19 @@ template <int Q>
 __host__ __device__ constexpr double wforce(int i) { return 3.0 * omega<Q>(i); }
 
 enum { EOS_CS = 0, EOS_PIECEWISE = 1 };
+// psi taken at a solid neighbour in F_int and Q_ab (the paper leaves it open): the node's
+// own psi, the w-weighted mean over its fluid neighbours, or zero.
+// WALL_PSI_MIRROR: psi(x + e') with e' = e_i less every component along which the axis
+// neighbour of x is solid (for a flat wall the mirror image of x + e_i across the wall
+// plane of halfway bounce-back); psi of the node where e' = 0 or x + e' is solid.
+enum { WALL_PSI_NODE = 0, WALL_PSI_FLUID_MEAN = 1, WALL_PSI_ZERO = 2, WALL_PSI_MIRROR = 3 };
+
+// Index of the lattice velocity (ex, ey, ez) in the order of Eq. (1) (-1 if none).
+__host__ __device__ constexpr int vel_index(int ex, int ey, int ez) {
+    for (int k = 0; k < 27; ++k)
+        if (vel_x(k) == ex && vel_y(k) == ey && vel_z(k) == ez) return k;
+    return -1;
+}
 
 // Reciprocal and square root: in float32 the hardware instructions (v_rcp_f32,
 // v_sqrt_f32, about 1 ulp); in float64 the correctly rounded operations.
@@ -81,6 +94,7 @@ struct Phys {
     int var_nu;               // density-dependent viscosity, Eq. (24)
     R nu_v, dnu_drho, rho_v;  // nu = nu_v + dnu_drho (rho - rho_v)
     R bfx, bfy, bfz;          // body force
+    int wall_psi;             // WALL_PSI_*
 };
 
 // Square-root pseudopotential of Sec. II C, psi = sqrt(2 (p_EOS - rho c_s^2) / G), c = 1,
@@ -111,7 +125,10 @@ struct NodeForce {
 };
 
 // psi_nb[i] = psi(x + e_i) for i >= 1, negative where x + e_i is solid. A solid neighbour
-// takes psi of the node itself in F_int and Q_ab and counts in the wetting sum.
+// counts in the wetting sum and takes, in F_int and Q_ab, psi of the node itself
+// (WALL_PSI_NODE: its terms vanish), the w-weighted mean psi of the fluid neighbours or 0:
+// the main loop sums the fluid neighbours only, and for the two other readings a second
+// pass adds (psi_wall - psi0) times the solid neighbours' first and second moments of w e.
 // SOLIDS = false: the lattice has no solid node (psi_nb is never negative), so the solid
 // tests and the wetting sums drop out at compile time; the arithmetic of every remaining
 // term is unchanged, so both forms give bitwise equal results on such a lattice.
@@ -144,6 +161,73 @@ __device__ __forceinline__ NodeForce<R> node_force_sums(R psi0, const R* psi_nb,
         if (ex) sx += ex > 0 ? ws : -ws;
         if (ey) sy += ey > 0 ? ws : -ws;
         if (ez) sz += ez > 0 ? ws : -ws;
+    }
+    if (SOLIDS && P.wall_psi == WALL_PSI_MIRROR) {
+        // solidity of the six axis neighbours decides which components of a solid link to
+        // drop; the image's psi is chosen by selects among the compile-time candidates
+        const bool sol[3][2] = {{psi_nb[2] < R(0), psi_nb[1] < R(0)},
+                                {psi_nb[4] < R(0), psi_nb[3] < R(0)},
+                                {psi_nb[6] < R(0), psi_nb[5] < R(0)}};
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            if (!(psi_nb[i] < R(0))) continue;
+            const int e[3] = {vel_x(i), vel_y(i), vel_z(i)};
+            bool keep[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) keep[a] = e[a] != 0 && !sol[a][e[a] > 0];
+            R pm = psi0;
+#pragma unroll
+            for (int mask = 1; mask < 8; ++mask) {
+                // candidate e' keeps the components in mask (only those e has)
+                const int cx = (mask & 1) ? e[0] : 0, cy = (mask & 2) ? e[1] : 0,
+                          cz = (mask & 4) ? e[2] : 0;
+                if (((mask & 1) && !e[0]) || ((mask & 2) && !e[1]) || ((mask & 4) && !e[2]))
+                    continue;
+                const int j = vel_index(cx, cy, cz);
+                if (j < 1 || j >= Q) continue;
+                const bool pick = keep[0] == ((mask & 1) != 0) && keep[1] == ((mask & 2) != 0) &&
+                                  keep[2] == ((mask & 4) != 0);
+                if (pick && !(psi_nb[j] < R(0))) pm = psi_nb[j];
+            }
+            const R w = R(wforce<Q>(i));
+            const R wd = w * (pm - psi0);
+            if (e[0]) ax += e[0] > 0 ? wd : -wd;
+            if (e[1]) ay += e[1] > 0 ? wd : -wd;
+            if (e[2]) az += e[2] > 0 ? wd : -wd;
+            if (WITH_Q) {
+                if (e[0]) qxx += wd;
+                if (e[1]) qyy += wd;
+                if (e[2]) qzz += wd;
+                if (e[0] && e[1]) qxy += e[0] * e[1] > 0 ? wd : -wd;
+                if (e[0] && e[2]) qxz += e[0] * e[2] > 0 ? wd : -wd;
+                if (e[1] && e[2]) qyz += e[1] * e[2] > 0 ? wd : -wd;
+            }
+        }
+    }
+    if (SOLIDS && (P.wall_psi == WALL_PSI_FLUID_MEAN || P.wall_psi == WALL_PSI_ZERO)) {
+        R wf = 0, pf = 0;                     // sum over fluid neighbours of w, w (psi - psi0)
+        R txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;   // solid: sum w e_a e_b
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const R w = R(wforce<Q>(i));
+            const bool solid = psi_nb[i] < R(0);
+            const int ex = vel_x(i), ey = vel_y(i), ez = vel_z(i);
+            if (!solid) { wf += w; pf += w * (psi_nb[i] - psi0); }
+            if (WITH_Q && solid) {
+                if (ex) txx += w;
+                if (ey) tyy += w;
+                if (ez) tzz += w;
+                if (ex && ey) txy += ex * ey > 0 ? w : -w;
+                if (ex && ez) txz += ex * ez > 0 ? w : -w;
+                if (ey && ez) tyz += ey * ez > 0 ? w : -w;
+            }
+        }
+        const R dm = P.wall_psi == WALL_PSI_ZERO ? -psi0 : (wf > R(0) ? pf / wf : R(0));
+        ax += dm * sx; ay += dm * sy; az += dm * sz;
+        if (WITH_Q) {
+            qxx += dm * txx; qyy += dm * tyy; qzz += dm * tzz;
+            qxy += dm * txy; qxz += dm * txz; qyz += dm * tyz;
+        }
     }
     NodeForce<R> nf;
     // Eq. (16): F_int = -G psi sum w psi(x+e) e; sum w e = 0 lets psi(x+e) become the

@@ -19,6 +19,7 @@ LBM_FP64, LBM_FP32, LBM_FP16 = 0, 1, 2
 LBM_EOS_CS, LBM_EOS_PIECEWISE = 0, 1
 LBM_BC_PERIODIC, LBM_BC_WALL = 0, 1
 LBM_STEP_FUSED, LBM_STEP_TWO_PASS = 0, 1
+LBM_WALL_PSI_NODE, LBM_WALL_PSI_FLUID_MEAN, LBM_WALL_PSI_ZERO, LBM_WALL_PSI_MIRROR = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
                 -4: "LBM_ENONFINITE", -5: "LBM_ESTATE"}
@@ -49,6 +50,7 @@ class lbm_params(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("reduce_every", ctypes.c_int32),
         ("step_kernel", ctypes.c_int32),
+        ("wall_psi", ctypes.c_int32),
     ]
 
 

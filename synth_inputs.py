@@ -29,6 +29,7 @@ class Workload:
     rates: str = "paper"              # "paper": s2b = s3b = 0.6, others 1.2; "unit": all 1
     walls: tuple = ()                 # e.g. ("z_lo", "z_hi")
     cylinder: tuple = None            # (y_c, z_c, r) of an x-aligned cylinder
+    wall_psi: str = "mirror"          # psi at solid neighbours: mirror, node, fluid_mean, zero
     R: float = 8.0                    # droplet radius
     W: float = 5.0                    # interface width
     centre: tuple = None              # None: box centre (nx/2, ny/2, nz/2)
@@ -69,16 +70,20 @@ LAPLACE_256 = Workload("laplace-droplet-256^3-d3q19", 19, 256, 256, 256, T_over_
                        rates="unit", R=40.0, W=5.0, noise=0.01, seed=0, steps=5000)
 
 # Droplet impact on a flat wall: 384x384x192, walls at z = 0 and z = 191, 90 degree
-# contact angle (G_ads = 0), R = 40 at z = 50, U_z = -0.05, CS EOS at 0.55 T_c.
+# contact angle (G_ads = 0: a neutral wall with psi at the wall read at its mirror image),
+# R = 40 at z = 50, U_z = -0.05, CS EOS at 0.55 T_c, nu = 0.001 (Re = 2000).
 IMPACT_384 = Workload("impact-384x384x192-d3q19", 19, 384, 384, 192, T_over_Tc=0.55,
                       rates="paper", walls=("z_lo", "z_hi"), R=40.0, W=5.0,
                       centre=(192, 192, 50), U=(0.0, 0.0, -0.05), nu=0.001, steps=20000)
 
-# D3Q27 impact on a wall with an x-aligned cylinder: 320x256x192, CS at 0.6 T_c.
+# D3Q27 impact on a wall with an x-aligned cylinder: 320x256x192, CS at 0.6 T_c. The
+# configuration's 160 degree wall lies above the largest static angle this EOS holds (a
+# sessile drop: 146.5 degrees at G_ads = 0.24, about 150 at 0.26, detached from 0.3), so the
+# wall takes G_ads = 0.28, just below detachment.
 CYLINDER_D3Q27 = Workload("cylinder-impact-320x256x192-d3q27", 27, 320, 256, 192,
                           T_over_Tc=0.6, rates="paper", walls=("z_lo", "z_hi"),
                           cylinder=(128.0, 20.0, 20.0), R=30.0, W=5.0,
-                          centre=(160, 128, 80), U=(0.0, 0.0, -0.04), G_ads=0.2, steps=15000)
+                          centre=(160, 128, 80), U=(0.0, 0.0, -0.04), G_ads=0.28, steps=15000)
 
 
 def random_fields(shape, seed, rho_lo=0.02, rho_hi=0.4, u_amp=0.02):

@@ -20,7 +20,7 @@ def oracle_eos(w):
 def oracle_params(w, **over):
     kw = dict(Q=w.Q, nx=w.nx, ny=w.ny, nz=w.nz, eos=oracle_eos(w), G=w.G, sigma=w.sigma,
               kappa=w.kappa, G_ads=w.G_ads, nu_l=w.nu, walls={k: True for k in w.walls},
-              cylinder=w.cylinder, **RATES[w.rates])
+              cylinder=w.cylinder, wall_psi=w.wall_psi, **RATES[w.rates])
     kw.update(over)
     return olbm.Params(**kw)
 
@@ -53,6 +53,8 @@ def gpu_params(w, storage="fp64", rho_ref=0.0, **over):
     for name in w.walls:
         ax, side = name.split("_")
         p.bc[axes[ax]][0 if side == "lo" else 1] = L.LBM_BC_WALL
+    p.wall_psi = {"node": L.LBM_WALL_PSI_NODE, "fluid_mean": L.LBM_WALL_PSI_FLUID_MEAN,
+                  "zero": L.LBM_WALL_PSI_ZERO, "mirror": L.LBM_WALL_PSI_MIRROR}[w.wall_psi]
     if w.cylinder is not None:
         p.cylinder = 1
         p.cyl_y, p.cyl_z, p.cyl_r = w.cylinder

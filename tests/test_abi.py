@@ -121,6 +121,7 @@ def _bad(**changes):
     (dict(bc=3), "boundary"),
     (dict(reduce_every=-1), "reduce_every"),
     (dict(step_kernel=9), "step_kernel"),
+    (dict(wall_psi=4), "wall_psi"),
     (dict(T_over_Tc=1.2), "two-phase"),
 ])
 def test_create_rejects_invalid_parameters_before_touching_the_device(changes, message):

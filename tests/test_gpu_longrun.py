@@ -1,0 +1,136 @@
+"""Long runs in reduced-precision storage against FP64, through the quantities the
+benchmark's target names (coexistence densities, Laplace pressure, spreading diameter),
+and the droplet-impact configuration at full size.
+
+Bars (stated per test): FP32 shifted storage must reproduce the FP64 run's observables
+to the rounding level of its populations carried over thousands of steps; FP16 shifted
+storage is held to the looser bars its 11-bit significand allows."""
+import math
+
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from tests.helpers import gpu_params, maxwell
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2306_16274_amd import lbm
+    lbm.library()
+    return lbm
+
+
+def _radius(n, c):
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    return np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2)
+
+
+def test_static_droplet_observables_fp32_fp16_vs_fp64(L):
+    """Static droplet R0 = 38 in a 180^3 periodic box, the paper's piecewise EOS (Sec.
+    III A), D3Q19 with the printed rates at nu = 0.1, 8000 steps in FP64, FP32 and FP16
+    shifted storage (rho_ref = 0.001): liquid density at the centre, vapour density
+    (mean beyond R + 15), Laplace pressure jump of Eq. (17) and liquid volume.
+    FP32: every observable within 1e-4 relative of FP64. FP16: within 5 % (vapour 20 %)."""
+    import tests.test_gpu_physics as tp
+    n, R = 180, 38.0
+    c = n / 2
+    r = _radius(n, c)
+    obs = {}
+    for storage in ("fp64", "fp32", "fp16"):
+        p = tp.piecewise(L, (n, n, n), "fp32" if storage == "fp16" else storage)
+        if storage == "fp16":
+            p.storage = L.LBM_FP16
+        p.rho_ref = 0.0 if storage == "fp64" else 0.001
+        with L.Lattice(p) as lat:
+            lat.init_droplet(c, c, c, R, 5.0, 1.0, 0.001)
+            lat.step(8000)
+            m = lat.moments(want=("rho", "p"))
+        rho, pr = m["rho"], m["p"]
+        obs[storage] = dict(rho_l=float(rho[int(c), int(c), int(c)]),
+                            rho_v=float(rho[r > R + 15].mean()),
+                            dp=float(pr[r <= R / 3].mean() - pr[r >= R + 15].mean()),
+                            vol=float(np.clip((rho - 0.001) / 0.999, 0, 1).sum()))
+    ref = obs["fp64"]
+    print("static droplet observables", obs)
+    for k, v in ref.items():
+        assert abs(obs["fp32"][k] - v) / abs(v) < 1e-4, (k, obs["fp32"][k], v)
+        bar = 0.20 if k == "rho_v" else 0.05
+        assert abs(obs["fp16"][k] - v) / abs(v) < bar, (k, obs["fp16"][k], v)
+
+
+def test_impact_observables_fp32_fp16_vs_fp64(L):
+    """The super-hydrophobic impact of Sec. IV B (R0 = 50, U = 0.0439, G_ads = 0.23, D3Q27,
+    piecewise EOS, nu_l = 0.0075, nu_v = 0.05, box 256 x 256 x 250) in FP64, FP32 and FP16
+    shifted storage: contact time, maximum spreading diameter, the spreading-diameter
+    series sampled every 100 steps, and the liquid volume at the end.
+    FP32: contact time and maximum spreading within 1 %, the series within 2 % of FP64's
+    largest value at every sample, volume within 1e-4 (measured: contact time and maximum
+    spreading equal to four digits, volume 0.99908 against 0.99909). FP16: contact time
+    within 10 %, maximum spreading within 3 %, volume within 5 % (measured: +7.5 %, +1.4 %,
+    -3.9 %: the liquid loses mass through the rounding of populations to 11 bits)."""
+    from paper_2306_16274_amd import impact
+    gamma = 0.01007
+    tau = impact.capillary_time(1.0, 50.0, gamma)
+    res = {}
+    for storage in ("fp64", "fp32", "fp16"):
+        case = impact.ImpactCase(nx=256, ny=256, U=0.0439, G_ads=0.23, storage=storage)
+        o = impact.run_impact(case, 16000, every=100, keep_going=False)
+        assert o["t_contact"] is not None and o["t_detach"] is not None, storage
+        res[storage] = dict(tc=(o["t_detach"] - o["t_contact"]) / tau, D=np.array(o["D_f"]),
+                            vol=o["volume"][-1] / o["volume"][0])
+    r64, r32, r16 = res["fp64"], res["fp32"], res["fp16"]
+    print({k: (round(v["tc"], 4), round(float(v["D"].max()), 2), round(v["vol"], 5))
+           for k, v in res.items()})
+    assert abs(r32["tc"] - r64["tc"]) / r64["tc"] < 0.01
+    assert abs(r32["D"].max() - r64["D"].max()) / r64["D"].max() < 0.01
+    n = min(len(r32["D"]), len(r64["D"]))
+    assert np.max(np.abs(r32["D"][:n] - r64["D"][:n])) < 0.02 * r64["D"].max()
+    assert abs(r32["vol"] - r64["vol"]) < 1e-4
+    assert abs(r16["tc"] - r64["tc"]) / r64["tc"] < 0.10
+    assert abs(r16["D"].max() - r64["D"].max()) / r64["D"].max() < 0.03
+    assert abs(r16["vol"] - r64["vol"]) < 0.05
+
+
+def test_droplet_impact_384_full_size(L):
+    """The droplet-impact configuration at full size: 384 x 384 x 192 D3Q19 in FP32
+    shifted storage, walls at z = 0 and 191, CS EOS at 0.55 T_c, R = 40 at z = 50 falling at
+    0.05, a 90 degree wall (G_ads = 0 with the mirror reading of psi at the wall).
+    With the configuration's nu_l = 0.001 (Re = 2000) the run is reported non-finite by the
+    health check within 200 steps (so it is on D3Q27 and with s4 = 1 or a vapour viscosity
+    of 0.05). With the fallback the survey names, the paper's own nu_l = 0.0035 (Sec. IV A),
+    and nu_v = 0.05 through Eq. (24) and s4 = 1 (D3Q19 is linearly unstable below
+    nu = 0.05 with the printed rates), it runs the 20000 steps with the spreading diameter
+    recorded every 100 steps: the film spreads to 3.0-4.5 R before it retracts, and the
+    mass drifts by less than 1e-5."""
+    from paper_2306_16274_amd import impact
+    w = si.IMPACT_384
+    rv, rl = maxwell(w)
+    p = gpu_params(w, "fp32", rho_ref=rv, reduce_every=100)
+    with L.Lattice(p) as lat:
+        lat.init_droplet(*w.droplet_centre(), w.R, w.W, rl, rv, *w.U, w.noise, w.seed)
+        with pytest.raises(L.LbmError) as ei:
+            lat.step(200)
+            lat.synchronize()
+        assert ei.value.status == L.LBM_ENONFINITE
+    p = gpu_params(w, "fp32", rho_ref=rv, reduce_every=100, s4=1.0, nu_l=0.0035, nu_v=0.05,
+                   rho_l=rl, rho_v=rv)
+    thr = 0.5 * (rv + rl)
+    D = []
+    with L.Lattice(p) as lat:
+        lat.init_droplet(*w.droplet_centre(), w.R, w.W, rl, rv, *w.U, w.noise, w.seed)
+        m0 = lat.moments(want=("totals",))["totals"][0]
+        for _ in range(200):
+            lat.step(100)
+            D.append(impact.spreading_diameter(lat.liquid_stats(thr, rv, rl)[0], 1))
+        m1 = lat.moments(want=("totals",))["totals"][0]
+    D = np.array(D)
+    print(f"384^2 x 192 impact: D_max/R {D.max() / w.R:.2f}, D_f/R every 1000 steps "
+          f"{np.round(D[9::10] / w.R, 2).tolist()}, mass drift {(m1 - m0) / m0:+.2e}")
+    assert 3.0 < D.max() / w.R < 4.5
+    assert D[-1] < D.max()
+    assert abs(m1 - m0) / m0 < 1e-5

@@ -117,6 +117,30 @@ def test_fp64_brute_force_tiny_box(L, Q, geometry, kernel):
 
 @KERNELS
 @pytest.mark.parametrize("Q", [19, 27])
+@pytest.mark.parametrize("reading", ["fluid_mean", "zero", "node"])
+def test_fp64_brute_force_wall_psi_readings(L, Q, reading, kernel):
+    """The other readings of psi at solid neighbours (w-weighted mean over the fluid
+    neighbours; zero; the node's own psi) on the walled 9x8x7 box with a cylinder, wetting,
+    kappa and nu(rho) (the default mirror reading runs in every other parity test):
+    1 and 20 steps against the oracle, populations to 1e-13 absolute."""
+    w = si.Workload("tiny", Q, 9, 8, 7, sigma=0.12, kappa=0.3, G_ads=0.15, nu=0.05,
+                    T_over_Tc=0.6, walls=("z_lo", "z_hi"), cylinder=(4.0, 3.0, 1.2),
+                    wall_psi=reading)
+    over = dict(nu_v=0.15, rho_l=0.4, rho_v=0.01)
+    rho, u = si.random_fields(w.shape, seed=3, rho_lo=0.05, rho_hi=0.4)
+    P, solid, f0 = oracle_state_from_fields(w, rho, u, **over)
+    f0 = f0 * si.random_factors(Q, w.shape, seed=3, amp=0.02)
+    for steps in (1, 20):
+        fo = olbm.run(f0, P, steps, solid)
+        g, mom = run_pair(L, w, f0, steps, step_kernel=kernel_code(L, kernel), **over)
+        assert abs_err(g, fo) < 1e-13, steps
+        ro, uo, _, _ = olbm.moments(fo, P, solid)
+        assert rel_err(mom["rho"], ro, ~solid) < 1e-12
+        assert abs_err(mom["u"], uo, ~solid) < 1e-13
+
+
+@KERNELS
+@pytest.mark.parametrize("Q", [19, 27])
 @pytest.mark.parametrize("geometry", ["periodic", "walls"])
 def test_fp64_brute_force_piecewise_eos(L, Q, geometry, kernel):
     """The paper's own piecewise-linear EOS (Sec. III A, Eqs. (18)-(20): slopes 1/6, -1/120,

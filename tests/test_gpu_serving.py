@@ -224,3 +224,21 @@ def test_serving_evicts_a_failed_request(L, monkeypatch, mode):
         c = by_id[r["id"]]
         assert r["finite"] and r["mass"] == c["mass"], r["id"]
         assert r["spread_diameter"] == c["spread_diameter"], r["id"]
+
+
+@pytest.mark.parametrize("theta", [60.0, 140.0])
+def test_serving_contact_angle_calibration(L, theta):
+    """Spot check of the serving calibration: a sessile drop of the serving physics on a
+    wall with G_ads = g_ads_for_angle(theta) settles to theta within 4 degrees."""
+    from paper_2306_16274_amd import impact, serving
+    req = dict(L=100, theta=theta, R=20.0, U=0.0, steps=8000)
+    p, rv, rl = serving.request_params(req, "fp32")
+    p.nz = 60
+    thr = 0.5 * (rv + rl)
+    with L.Lattice(p) as lat:
+        lat.init_droplet(50.0, 50.0, 0.5 + 12.0, 20.0, 5.0, rl, rv)
+        lat.step(8000)
+        counts = lat.liquid_stats(thr, rv, rl)[0]
+    measured = impact.contact_angle_from_planes(counts)[0]
+    print(f"serving wall for {theta} degrees: G_ads {p.G_ads:.4f}, measured {measured:.1f}")
+    assert abs(measured - theta) < 4.0

@@ -126,3 +126,107 @@ def test_laplace_law_and_surface_tension_scales_with_one_minus_kappa():
     assert abs(c0) < 0.2 * g0 / 7 and abs(c5) < 0.2 * g5 / 7
     # the quasi-steady states after 1500 steps give 0.46 here; 48^2 boxes at 2000 steps 0.48
     assert abs(g5 / g0 - 0.5) < 0.075
+
+
+@pytest.mark.parametrize("reading", ["node", "fluid_mean", "zero", "mirror"])
+@Q_BOTH
+def test_wall_psi_readings_brute_force(Q, reading):
+    """psi at solid neighbours (a reading: the paper leaves it open) and the resulting F_int
+    and Q_ab, node by node with explicit loops over the lattice velocities on a tiny box with
+    a wall and a cylinder, against the vectorised oracle."""
+    P = lbm.Params(Q=Q, nx=5, ny=6, nz=7, eos=eos.CarnahanStarling(0.5, 4, 1, 0.6),
+                   kappa=0.4, G_ads=0.17, walls={"z_lo": True}, cylinder=(3.0, 4.0, 1.2),
+                   wall_psi=reading)
+    solid = lbm.solid_mask(P)
+    rng = np.random.default_rng(3)
+    psi = np.where(solid, 0.0, rng.uniform(0.05, 0.6, P.shape))
+    F_int, F_ads, Qab, _ = lbm.forces(psi, solid, P)
+    lat = P.lat
+    for z in range(P.nz):
+        for y in range(P.ny):
+            for x in range(P.nx):
+                if solid[z, y, x]:
+                    continue
+                nbs = []
+                for i in range(1, Q):
+                    ex, ey, ez = (int(c) for c in lat.e[i])
+                    zz, yy, xx = (z + ez) % P.nz, (y + ey) % P.ny, (x + ex) % P.nx
+                    nbs.append((i, bool(solid[zz, yy, xx]), float(psi[zz, yy, xx])))
+                p0 = float(psi[z, y, x])
+                fluid = [(lat.w[i], v) for i, s, v in nbs if not s]
+                if reading == "node":
+                    pw = p0
+                elif reading == "zero":
+                    pw = 0.0
+                elif reading == "fluid_mean":
+                    pw = sum(w * v for w, v in fluid) / sum(w for w, _ in fluid)
+
+                def at(d):
+                    zz, yy, xx = (z + d[2]) % P.nz, (y + d[1]) % P.ny, (x + d[0]) % P.nx
+                    return bool(solid[zz, yy, xx]), float(psi[zz, yy, xx])
+
+                def mirror(ei):
+                    ep = [c if c != 0 and not at([c if a == b else 0 for b in range(3)])[0]
+                          else 0 for a, c in enumerate(ei)]
+                    if not any(ep) or at(ep)[0]:
+                        return p0
+                    return at(ep)[1]
+                f = np.zeros(3)
+                q = np.zeros((3, 3))
+                fa = np.zeros(3)
+                for i, s, v in nbs:
+                    e = lat.e[i].astype(float)
+                    if reading == "mirror" and s:
+                        pw = mirror([int(c) for c in lat.e[i]])
+                    pv = pw if s else v
+                    f += lat.w[i] * pv * e
+                    q += lat.w[i] * (pv - p0) * np.outer(e, e)
+                    if s:
+                        fa += lat.w[i] * e
+                f *= -P.G * p0
+                q *= P.kappa * P.G / 2.0 * p0
+                fa *= -P.G_ads * p0 * p0
+                assert np.allclose(F_int[:, z, y, x], f, rtol=0, atol=1e-15)
+                assert np.allclose(F_ads[:, z, y, x], fa, rtol=0, atol=1e-15)
+                for k, (a, b) in dict(xx=(0, 0), yy=(1, 1), zz=(2, 2), xy=(0, 1), xz=(0, 2),
+                                      yz=(1, 2)).items():
+                    assert abs(Qab[k][z, y, x] - q[a, b]) < 1e-15
+
+
+@Q_BOTH
+def test_fluid_mean_wall_is_neutral_for_a_uniform_fluid(Q):
+    """With psi at solid neighbours the mean over the fluid neighbours, a uniform fluid next
+    to walls and a cylinder (G_ads = 0) feels no force and stays at rest, as with the node's
+    own psi; psi = 0 at solid neighbours instead pulls the fluid towards the bulk."""
+    for reading, neutral in (("fluid_mean", True), ("zero", False)):
+        P = lbm.Params(Q=Q, nx=6, ny=7, nz=8, eos=eos.CarnahanStarling(0.5, 4, 1, 0.6),
+                       sigma=0.1, kappa=0.3, nu_l=0.08, walls={"z_lo": True, "z_hi": True},
+                       cylinder=(3.0, 4.0, 1.5), wall_psi=reading)
+        solid = lbm.solid_mask(P)
+        f = lbm.equilibrium_populations(P, np.full(P.shape, 0.3), np.zeros((3,) + P.shape),
+                                        solid)
+        F = lbm.macroscopic(f, P, solid)["F"]
+        assert (np.abs(F).max() < 1e-15) == neutral, reading
+
+
+@Q_BOTH
+def test_mirror_wall_is_a_symmetry_plane(Q):
+    """With the "mirror" reading, a flat wall halfway between the solid layer z = 0 and the
+    fluid layer z = 1 acts on F_int and Q_ab like a symmetry plane: the first fluid layer of
+    a box with a wall feels exactly the forces of the same layer in a periodic box holding
+    the state mirrored across z = 1/2 (any psi field varying in x, y and z)."""
+    nx, ny, nz = 6, 5, 8
+    P = lbm.Params(Q=Q, nx=nx, ny=ny, nz=nz, eos=eos.CarnahanStarling(0.5, 4, 1, 0.6),
+                   kappa=0.4, walls={"z_lo": True}, wall_psi="mirror")
+    solid = lbm.solid_mask(P)
+    rng = np.random.default_rng(9)
+    psi = np.where(solid, 0.0, rng.uniform(0.05, 0.6, P.shape))
+    F, _, Qab, _ = lbm.forces(psi, solid, P)
+    # periodic box of 2 (nz - 1) planes: z = 1..nz-1, then the same planes reversed
+    body = psi[1:]
+    Pm = lbm.Params(Q=Q, nx=nx, ny=ny, nz=2 * (nz - 1), eos=P.eos, kappa=0.4)
+    psim = np.concatenate([body, body[::-1]], axis=0)
+    Fm, _, Qm, _ = lbm.forces(psim, np.zeros(Pm.shape, dtype=bool), Pm)
+    assert np.allclose(F[:, 1], Fm[:, 0], rtol=0, atol=1e-15)
+    for k in Qab:
+        assert np.allclose(Qab[k][1], Qm[k][0], rtol=0, atol=1e-15)

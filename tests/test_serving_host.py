@@ -104,10 +104,16 @@ def test_steps_of_rounds_up_to_the_quantum():
     assert serving.steps_of({"steps": 1}) == serving.STEP_QUANTUM
 
 
-def test_contact_angle_map_passes_through_the_paper_points():
-    assert serving.g_ads_for_angle(90.0) == 0.0
-    assert serving.g_ads_for_angle(157.0) == pytest.approx(0.23)
-    assert serving.g_ads_for_angle(60.0) < 0.0 < serving.g_ads_for_angle(120.0)
+def test_contact_angle_map_interpolates_the_calibration():
+    """The angle -> G_ads map goes through every calibration point, is increasing, puts
+    the measured neutral wall at G_ads = 0 and extends the end segments beyond them."""
+    for g, th in serving.CALIBRATION:
+        assert serving.g_ads_for_angle(th) == pytest.approx(g, abs=1e-12)
+    ths = np.linspace(60.0, 160.0, 101)
+    gs = [serving.g_ads_for_angle(t) for t in ths]
+    assert all(b > a for a, b in zip(gs, gs[1:]))
+    assert abs(serving.g_ads_for_angle(90.0)) < 0.002
+    assert 0.2 < serving.g_ads_for_angle(160.0) < 0.25
 
 
 def test_request_params_use_the_coexistence_densities():
