@@ -14,8 +14,7 @@ and its exact rational inverse; the formulas follow the paper's order and notati
 * ``eos``         piecewise-linear and Carnahan-Starling pressure, square-root psi,
                   Maxwell coexistence densities                              (Sec. II C, Sec. III A)
 * ``lbm``         forces, collision in moment space, streaming with halfway bounce-back,
-                  initial state, macroscopic moments                          (Sec. II, App. B, Sec. III E)
-* ``diagnostics`` Laplace pressure jump, coexistence densities, liquid volume, spreading
-                  diameter                                                     (Sec. III-IV)
+                  initial state, macroscopic moments, totals and the liquid
+                  diagnostics (liquid nodes per plane, in contact, volume)     (Sec. II, App. B, Sec. III E, IV)
 * ``splitmix``    SplitMix64 counter generator for the interface noise of the initial state
 """

@@ -72,7 +72,10 @@ static double eos_rho_max(const lbm_params& p) {
 }
 
 // integral of p(rho)/rho^2 over [a, b] with composite 8-point Gauss-Legendre in ln(rho);
-// for the piecewise EOS the interval is split at its knees (p is only piecewise smooth)
+// for the piecewise EOS the interval is split at its knees (p is only piecewise smooth).
+// Nodes and weights of the 8-point rule on [-1, 1] (the roots of the Legendre polynomial
+// P_8 and w_j = 2 / ((1 - x_j^2) P_8'(x_j)^2), as tabulated in Abramowitz and Stegun,
+// Handbook of Mathematical Functions, Table 25.4); the positive half, used symmetrically.
 static double int_smooth(const lbm_params& p, double a, double b) {
     static const double xg[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267,
                                  0.9602898564975363};
