@@ -438,6 +438,36 @@ def test_fused_prefetch_tiles_bitwise_equal_plain_tiles(L, monkeypatch, geom, Q,
         assert np.array_equal(out[("3", None)], out[key]), key
 
 
+@pytest.mark.parametrize("geom", ["periodic", "walls", "cylinder"])
+@pytest.mark.parametrize("Q", [19, 27])
+def test_fp64_every_launch_configuration_matches_oracle(L, monkeypatch, Q, geom):
+    """Every FP64 launch configuration of the fused step on a 256-wide box (ragged y extent:
+    10 rows; 3 z-chunks of 7 planes over nz = 20) against the oracle: 12 steps from the
+    oracle's initial state, populations to 1e-13 absolute. Each configuration is its own
+    kernel instantiation (full-row 256x2 and 256x4 tiles, the prefetching 256x2 tile, 32x8,
+    64x4, 64x8), so a wrong result of any one of them cannot hide behind the others."""
+    walls = {"periodic": (), "walls": ("z_lo", "z_hi", "y_lo"), "cylinder": ("z_lo",)}[geom]
+    cyl = (5.0, 9.0, 3.0) if geom == "cylinder" else None
+    w = si.Workload("pf", Q, 256, 10, 20, T_over_Tc=0.7, walls=walls, cylinder=cyl, G_ads=0.05,
+                    R=7.0, centre=(128, 5, 10), U=(0.01, 0.0, -0.02), noise=0.01, seed=9, nu=0.08,
+                    kappa=0.2)
+    rv, rl = maxwell(w)
+    P = oracle_params(w)
+    solid = olbm.solid_mask(P)
+    rho, u = olbm.droplet_fields(P, *w.droplet_centre(), w.R, w.W, rl, rv, U=w.U,
+                                 noise_amp=w.noise, seed=w.seed)
+    f0 = olbm.equilibrium_populations(P, rho, u, solid)
+    fo = olbm.run(f0, P, 12, solid)
+    monkeypatch.setenv("LBM_FUSED_ZC", "7")
+    for cfg in ("0", "1", "2", "3", "4", "9", "10"):
+        monkeypatch.setenv("LBM_FUSED_CONFIG", cfg)
+        with L.Lattice(gpu_params(w, "fp64")) as lat:
+            lat.set_populations(f0)
+            lat.step(12)
+            g = lat.get_populations()
+        assert abs_err(g, fo) < 1e-13, cfg
+
+
 @pytest.mark.parametrize("storage", ["fp32", "fp16"])
 @pytest.mark.parametrize("geom", ["periodic", "walls", "cylinder"])
 @pytest.mark.parametrize("Q", [19, 27])
