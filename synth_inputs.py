@@ -65,15 +65,18 @@ STATIC_32 = Workload("static-droplet-32^3-d3q19", 19, 32, 32, 32, T_over_Tc=0.7,
 # noise in the interface band. The headline throughput workload. Non-viscous rates 1: with
 # the paper's rate set (bulk 0.6, others 1.2) droplets of R >= 30 at this temperature blow up
 # after 1100-1500 steps (the liquid density climbs to the psi^2 = 0 bound near 0.59), with
-# rates 1 they run the 5000 steps.
+# rates 1 they run. sigma = 0.1153: the value at which a flat interface of this EOS and rate
+# set settles on the Maxwell densities (0.1 leaves the vapour 88 % below them).
 LAPLACE_256 = Workload("laplace-droplet-256^3-d3q19", 19, 256, 256, 256, T_over_Tc=0.5,
-                       rates="unit", R=40.0, W=5.0, noise=0.01, seed=0, steps=5000)
+                       rates="unit", sigma=0.1153, R=40.0, W=5.0, noise=0.01, seed=0,
+                       steps=5000)
 
 # Droplet impact on a flat wall: 384x384x192, walls at z = 0 and z = 191, 90 degree
 # contact angle (G_ads = 0: a neutral wall with psi at the wall read at its mirror image),
-# R = 40 at z = 50, U_z = -0.05, CS EOS at 0.55 T_c, nu = 0.001 (Re = 2000).
+# R = 40 at z = 50, U_z = -0.05, CS EOS at 0.55 T_c, nu = 0.001 (Re = 2000); sigma = 0.119
+# puts a flat interface of this EOS and the paper's rates on the Maxwell densities.
 IMPACT_384 = Workload("impact-384x384x192-d3q19", 19, 384, 384, 192, T_over_Tc=0.55,
-                      rates="paper", walls=("z_lo", "z_hi"), R=40.0, W=5.0,
+                      rates="paper", sigma=0.119, walls=("z_lo", "z_hi"), R=40.0, W=5.0,
                       centre=(192, 192, 50), U=(0.0, 0.0, -0.05), nu=0.001, steps=20000)
 
 # D3Q27 impact on a wall with an x-aligned cylinder: 320x256x192, CS at 0.6 T_c. The
