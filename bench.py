@@ -4,7 +4,8 @@ One step is one time step of the whole hot path (streaming with bounce-back, den
 pseudopotential, interaction / wetting / surface-tension terms, moment-space collision,
 back-transform, store) over the lattice of the workload. The workload is a 256^3 D3Q19
 static droplet (Carnahan-Starling EOS at T = 0.5 T_c, all non-viscous relaxation rates 1,
-nu = 0.1, +-1 % interface noise), populations resident in HBM before timing starts.
+nu = 0.1, sigma = 0.1153 (the value at which a flat interface settles on the Maxwell
+densities), +-1 % interface noise), populations resident in HBM before timing starts.
 
 Prints one JSON line (rank 0): the FP32 shifted-storage throughput in MLUPS as `value`,
 the FP64 and FP16-shifted throughputs beside it, the HBM roofline of the dominant kernel

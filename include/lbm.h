@@ -71,7 +71,10 @@ typedef struct {
     /* Piecewise-linear EOS, Eq. (18): slopes and the two spinodal densities             */
     double pw_theta_v, pw_theta_m, pw_theta_l, pw_rho1, pw_rho2;
     double G;                 /* interaction strength of Eq. (16)                        */
-    double sigma;             /* mechanical-stability parameter of Eq. (B1)              */
+    double sigma;             /* mechanical-stability parameter of Eq. (B1); the paper's
+                                 0.1 is for its piecewise EOS: with Carnahan-Starling
+                                 (a = 0.5, b = 4) a flat interface settles on the Maxwell
+                                 densities at 0.115-0.119 for 0.5-0.7 T_c               */
     double kappa;             /* surface-tension tuning of Eq. (B2)                      */
     double G_ads;             /* fluid-solid interaction strength of Eq. (22)            */
     double nu_l, nu_v;        /* kinematic viscosity; nu_v != nu_l enables Eq. (24)      */
