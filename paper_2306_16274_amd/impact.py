@@ -161,7 +161,8 @@ def run_impact(case, steps, every=50, stream=None, log=None, keep_going=False, r
     z = 1 .. reach), liquid nodes in contact, liquid volume, liquid nodes in the planes
     z = 1..8, the lowest liquid plane and the liquid centroid height, plus t_contact (first
     sample in contact) and t_detach (first later sample out of contact, None while still in
-    contact). keep_going: sample until `steps` even after the droplet has left the solid."""
+    contact), and the total mass at the start (mass0) and the end (mass).
+    keep_going: sample until `steps` even after the droplet has left the solid."""
     p = case.params()
     if stream is not None:
         p.stream = stream
@@ -172,6 +173,7 @@ def run_impact(case, steps, every=50, stream=None, log=None, keep_going=False, r
     with L.Lattice(p, use_torch_stream=stream is None) as lat:
         cx, cy, cz = case.centre()
         lat.init_droplet(cx, cy, cz, case.R0, case.W, case.rho_l, case.rho_v, 0.0, 0.0, -case.U)
+        out["mass0"] = float(lat.moments(want=("totals",))["totals"][0])
         done = 0
         while True:
             cz_, wz, vol = lat.liquid_stats(thr, case.rho_v, case.rho_l, reach)

@@ -79,14 +79,14 @@ IMPACT_384 = Workload("impact-384x384x192-d3q19", 19, 384, 384, 192, T_over_Tc=0
                       rates="paper", sigma=0.119, walls=("z_lo", "z_hi"), R=40.0, W=5.0,
                       centre=(192, 192, 50), U=(0.0, 0.0, -0.05), nu=0.001, steps=20000)
 
-# D3Q27 impact on a wall with an x-aligned cylinder: 320x256x192, CS at 0.6 T_c. The
-# configuration's 160 degree wall lies above the largest static angle this EOS holds (a
-# sessile drop: 146.5 degrees at G_ads = 0.24, about 150 at 0.26, detached from 0.3), so the
-# wall takes G_ads = 0.28, just below detachment.
+# D3Q27 impact on a wall with an x-aligned cylinder: 320x256x192, CS at 0.6 T_c, sigma =
+# 0.1186 (a flat interface of this EOS and rate set settles on the Maxwell densities). The
+# configuration's 160 degree wall: a sessile drop (R = 25) stands at 143.4 degrees for
+# G_ads = 0.24, 157.6 at 0.27, 165.6 at 0.28 and leaves the wall from 0.32, so G_ads = 0.273.
 CYLINDER_D3Q27 = Workload("cylinder-impact-320x256x192-d3q27", 27, 320, 256, 192,
-                          T_over_Tc=0.6, rates="paper", walls=("z_lo", "z_hi"),
+                          T_over_Tc=0.6, rates="paper", sigma=0.1186, walls=("z_lo", "z_hi"),
                           cylinder=(128.0, 20.0, 20.0), R=30.0, W=5.0,
-                          centre=(160, 128, 80), U=(0.0, 0.0, -0.04), G_ads=0.28, steps=15000)
+                          centre=(160, 128, 80), U=(0.0, 0.0, -0.04), G_ads=0.273, steps=15000)
 
 
 def random_fields(shape, seed, rho_lo=0.02, rho_hi=0.4, u_amp=0.02):
