@@ -1,6 +1,7 @@
 // Batched stepping of many lattices (the serving loop's launch path): one launch per time
-// step over every member's tiles (k_step_fused_batch), steps_per_launch launches captured
-// once into a HIP graph. C ABI: lbm_batch_* in include/lbm.h.
+// step over every member's tiles (row tiles of run-time width, k_step_fused_batch_rows, for
+// FP32 members up to 384 wide; else 64x4 tiles, k_step_fused_batch), steps_per_launch
+// launches captured once into a HIP graph. C ABI: lbm_batch_* in include/lbm.h.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -13,6 +14,10 @@
 // Tile shapes of the batched kernel (index lbm_batch::tile) and the z-chunk depth.
 constexpr int kBatchTiles[2][2] = {{64, 4}, {32, 8}};
 constexpr int kBatchZC = 16;
+// Row tiles (k_step_fused_batch_rows): threads per workgroup (12 wavefronts: the walled
+// kernel fits the 168 VGPRs that leaves); members up to kRowsNT / 2
+// wide, 4-byte storage.
+constexpr int kRowsNT = 768;
 
 struct lbm_batch {
     std::vector<lbm_ctx*> ctx;
@@ -26,6 +31,7 @@ struct lbm_batch {
     long long blocks = 0;
     int geom = GEOM_WALLS;                // GEOM_MASK if any member has a cylinder
     int tile = 0;                         // index into kBatchTiles
+    bool rows = false;                    // row tiles of run-time width instead
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
@@ -75,13 +81,39 @@ static void launch_batch(const lbm_batch* b, hipStream_t s, const void* table, b
 }
 
 template <typename T>
+static void launch_batch_rows(const lbm_batch* b, hipStream_t s, const void* table, bool nt,
+                              int remap) {
+    if constexpr (sizeof(T) == 4) {
+        const dim3 grid((unsigned)b->blocks), block(kRowsNT);
+        const DomainDesc<T>* tb = (const DomainDesc<T>*)table;
+        const int nd = (int)b->ctx.size();
+        auto go = [&](auto geom, auto nts) {
+            hipLaunchKernelGGL((k_step_fused_batch_rows<19, T, decltype(geom)::value, kRowsNT,
+                                                        decltype(nts)::value>),
+                               grid, block, 0, s, tb, nd, remap);
+        };
+        using std::integral_constant;
+        if (b->geom == GEOM_MASK) {
+            if (nt) go(integral_constant<int, GEOM_MASK>{}, integral_constant<bool, true>{});
+            else go(integral_constant<int, GEOM_MASK>{}, integral_constant<bool, false>{});
+        } else {
+            if (nt) go(integral_constant<int, GEOM_WALLS>{}, integral_constant<bool, true>{});
+            else go(integral_constant<int, GEOM_WALLS>{}, integral_constant<bool, false>{});
+        }
+    }
+}
+
+template <typename T>
 static lbm_status build_tables(lbm_batch* b) {
     using R = typename Arith<T>::type;
     std::vector<DomainDesc<T>> t[2];
     long long block0 = 0;
     const int TX = kBatchTiles[b->tile][0], TY = kBatchTiles[b->tile][1];
     for (lbm_ctx* c : b->ctx) {
-        const int ntx = (c->p.nx + TX - 1) / TX, nty = (c->p.ny + TY - 1) / TY;
+        // row tiles: as many whole rows as the workgroup holds
+        const int rows = b->rows ? std::min(kRowsNT / c->p.nx, c->p.ny) : 0;
+        const int ntx = b->rows ? 1 : (c->p.nx + TX - 1) / TX;
+        const int nty = b->rows ? (c->p.ny + rows - 1) / rows : (c->p.ny + TY - 1) / TY;
         int zc = kBatchZC;
         if (const char* e = getenv("LBM_BATCH_ZC")) zc = std::max(1, atoi(e));    // tuning override
         zc = std::min(zc, c->p.nz);
@@ -95,6 +127,7 @@ static lbm_status build_tables(lbm_batch* b) {
             d.g = grid_of(c);
             d.P = P;
             d.ntx = ntx; d.nty = nty; d.zc = zc; d.block0 = (int)block0;
+            d.rows = rows;
             t[par].push_back(d);
         }
         block0 += nb;
@@ -129,7 +162,9 @@ static lbm_status build_tables(lbm_batch* b) {
     int remap = 1;
     if (const char* e = getenv("LBM_BATCH_REMAP")) remap = atoi(e) != 0;       // tuning override
     for (int s = 0; s < b->steps_per_launch; ++s) {
-        if (b->tile == 0)
+        if (b->rows)
+            launch_batch_rows<T>(b, cap, b->table[s & 1], nt, remap);
+        else if (b->tile == 0)
             launch_batch<T, kBatchTiles[0][0], kBatchTiles[0][1]>(b, cap, b->table[s & 1], pf, nt, remap);
         else
             launch_batch<T, kBatchTiles[1][0], kBatchTiles[1][1]>(b, cap, b->table[s & 1], pf, nt, remap);
@@ -185,6 +220,15 @@ extern "C" lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, int32_t 
     for (int i = 0; i < n; ++i)
         if (ctxs[i]->p.cylinder && ctxs[i]->any_solid) b->geom = GEOM_MASK;
     if (const char* e = getenv("LBM_BATCH_TILE")) b->tile = atoi(e) == 1 ? 1 : 0;   // tuning override
+    // Row tiles (the default where they apply: 4-byte storage, members at most kRowsNT / 2
+    // wide) against the 64x4 tiles, serving physics, GLUPS: 24 mixed sizes 64-192 26.8 vs
+    // 19.7, 8 x 128^3 29.0 vs 23.9, 32 x 64^3 28.6-29.0 vs 26.6, 2 x 192^3 27.8 vs 25.3 (no
+    // x-halo, whole rows on 128-byte lines where the width allows; 512-thread row tiles
+    // lost on 192-wide members, where only two rows fit).
+    bool rows_ok = storage == LBM_FP32;
+    for (int i = 0; i < n; ++i) rows_ok = rows_ok && ctxs[i]->p.nx <= kRowsNT / 2;
+    b->rows = rows_ok;
+    if (const char* e = getenv("LBM_BATCH_ROWS")) b->rows = rows_ok && atoi(e) != 0;   // tuning
     auto bail = [&](lbm_status s) { batch_free(b); delete b; return s; };
     hipError_t e = hipSetDevice(ctxs[0]->device);
     if (e == hipSuccess) {

@@ -877,6 +877,7 @@ struct DomainDesc {
     Grid g;
     Phys<typename Arith<T>::type> P;
     int ntx, nty, zc, block0;
+    int rows;                  // rows per tile of the row-tile kernel (k_step_fused_batch_rows)
 };
 
 // Many independent lattices advanced by one launch: workgroup b (after the XCD-contiguous
@@ -909,6 +910,224 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_batch_pf(const DomainDes
     const DomainDesc<T>& D = d[lo];
     fused_tile_pf<Q, T, GEOM, TX, TY, false, NTS>(D.fin, D.fout, D.links, D.g, D.P, b - D.block0,
                                                   D.ntx, D.nty, D.zc, 0);
+}
+
+
+// Full-row tiles of run-time width, for a batch of lattices of different widths (4- and
+// 2-byte storage). A workgroup of NT threads covers `rows` consecutive rows of a lattice of
+// width L = g.nx <= NT / 2 (rows = NT / L, or ny if smaller): lane tid owns node (tid mod L,
+// y0 + tid / L) for tid < rows L, each row wrapping inside itself in x as in the full-row
+// tiles, so that no x-halo is pulled; lanes beyond rows L own no node. The halo is the rows
+// y0 - 1 and y0 + rows (2 L <= NT nodes, one per thread). Own and halo populations of the
+// next plane are prefetched into LDS as in fused_tile_pf (without the nontemporal hint for
+// interior rows, whose lanes need not fill whole wavefronts here). The psi ring is flat:
+// (rows + 2) L <= NT + 2 L <= 2 NT cells per plane. Arithmetic per node as in fused_tile.
+template <int Q, typename T, int GEOM, int NT, bool NTS>
+__device__ __forceinline__ void fused_tile_rows(const T* __restrict__ fin, T* __restrict__ fout,
+                                                const uint32_t* __restrict__ links, const Grid& g,
+                                                const Phys<float>& P, int t, int rows, int nty,
+                                                int zc) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 2, "the LDS prefetch moves 2- or 4-byte elements");
+    static_assert(NT % 64 == 0, "whole wavefronts");
+    using R = float;
+    using S = typename PfSlot<T>::type;
+    __shared__ R ring[4][2 * NT];
+    __shared__ S pf_own[Q][NT];
+    __shared__ S pf_halo[Q][NT];
+    const uint32_t own_lds = lds_addr(&pf_own[0][(threadIdx.x >> 6) * 64]);
+    const uint32_t halo_lds = lds_addr(&pf_halo[0][(threadIdx.x >> 6) * 64]);
+
+    const int L = g.nx;
+    const int iy = t % nty;
+    const int iz = t / nty;
+    const int y0 = iy * rows, z0 = iz * zc;
+    const int z1 = min(z0 + zc, g.nz);
+    const int tid = threadIdx.x;
+    // lanes without a node take node 0's column and row (valid addresses; never stored, and
+    // they write no ring cell)
+    const bool own_lane = tid < rows * L;
+    const int lx = own_lane ? tid % L : 0, ly = own_lane ? tid / L : 0;
+    const int x = lx, y = y0 + ly;
+    const bool active = own_lane && y < g.ny;
+    auto wrapc = [](int c, int n) { c %= n; return c < 0 ? c + n : c; };
+    const int nxy = g.nx * g.ny;
+    const unsigned pst = (unsigned)g.stride * (unsigned)sizeof(T);
+    const bool has_halo = tid < 2 * L;
+    const int hx = has_halo ? tid % L : 0, hy = tid < L ? -1 : rows;
+    int oxy[9], hxy[9];
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            oxy[(dy + 1) * 3 + dx + 1] = wrapc(x + dx, L) + wrapc(y + dy, g.ny) * L;
+            hxy[(dy + 1) * 3 + dx + 1] = wrapc(hx + dx, L) + wrapc(y0 + hy + dy, g.ny) * L;
+        }
+    auto zoffs = [&](int zp, int* zo) {
+        zo[0] = wrapc(zp - 1, g.nz) * nxy;
+        zo[1] = wrapc(zp, g.nz) * nxy;
+        zo[2] = wrapc(zp + 1, g.nz) * nxy;
+    };
+    WallBits wo{0u, 0u, 0u}, wh{0u, 0u, 0u};
+    if (GEOM == GEOM_WALLS) {
+        wo.wx = wall_bits(x, L, g.walls, 0);
+        wo.wy = wall_bits(wrapc(y, g.ny), g.ny, g.walls, 1);
+        wh.wx = wall_bits(hx, L, g.walls, 0);
+        wh.wy = wall_bits(wrapc(y0 + hy, g.ny), g.ny, g.walls, 1);
+    }
+    auto zbits = [&](int zp) {
+        return GEOM == GEOM_WALLS ? wall_bits(wrapc(zp, g.nz), g.nz, g.walls, 2) : 0u;
+    };
+    auto psi_of = [&](R drho) { return pseudopotential<R>(P.rho_ref + drho, P); };
+    // ring cell of tile row r (0: halo row y0 - 1) and column c
+    auto cell = [&](int r, int c) { return r * L + c; };
+    auto col = [&](int dx) {
+        const int c = lx + dx;
+        return c < 0 ? c + L : (c >= L ? c - L : c);
+    };
+    // synchronous pulls (first two planes of the chunk)
+    auto own_psi = [&](int zp, int slot, R* v) {
+        int zo[3];
+        zoffs(zp, zo);
+        const WallBits wb{wo.wx, wo.wy, zbits(zp)};
+        const bool sld = node_solid<GEOM>(links, oxy[4] + zo[1], wb);
+        pull_loads<Q, T, R, GEOM>(fin, links, oxy, zo, wb, pst, v);
+        if (own_lane) ring[slot][cell(ly + 1, lx)] = sld ? R(-1) : psi_of(sum_q<Q, R>(v));
+    };
+    auto halo_psi = [&](int zp, int slot) {
+        if (!has_halo) return;
+        int zo[3];
+        zoffs(zp, zo);
+        const WallBits wb{wh.wx, wh.wy, zbits(zp)};
+        R hv;
+        if (node_solid<GEOM>(links, hxy[4] + zo[1], wb)) hv = R(-1);
+        else {
+            R v[Q];
+            pull_loads<Q, T, R, GEOM>(fin, links, hxy, zo, wb, pst, v);
+            hv = psi_of(sum_q<Q, R>(v));
+        }
+        ring[slot][cell(hy + 1, hx)] = hv;
+    };
+    // asynchronous pulls of plane zp into the LDS buffers (lanes with a node / a halo node)
+    auto prefetch_own = [&](int zp) {
+        if (!own_lane) return;
+        int zo[3];
+        zoffs(zp, zo);
+        const WallBits wb{wo.wx, wo.wy, zbits(zp)};
+        const unsigned lk = link_word<GEOM>(links, oxy[4] + zo[1]);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int e, pop;
+            pull_source<Q, GEOM>(i, oxy, zo, lk, wb, e, pop);
+            lds_dma<(int)sizeof(T), 0>(
+                reinterpret_cast<const char*>(fin) + ((unsigned)e * (unsigned)sizeof(T) + (unsigned)pop * pst),
+                own_lds + (uint32_t)(i * NT * sizeof(S)));
+        }
+    };
+    auto prefetch_halo = [&](int zp) {
+        if (!has_halo) return;
+        int zo[3];
+        zoffs(zp, zo);
+        const WallBits hb{wh.wx, wh.wy, zbits(zp)};
+        const unsigned lk = link_word<GEOM>(links, hxy[4] + zo[1]);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int e, pop;
+            pull_source<Q, GEOM>(i, hxy, zo, lk, hb, e, pop);
+            lds_dma<(int)sizeof(T), 0>(
+                reinterpret_cast<const char*>(fin) + ((unsigned)e * (unsigned)sizeof(T) + (unsigned)pop * pst),
+                halo_lds + (uint32_t)(i * NT * sizeof(S)));
+        }
+    };
+    auto take_halo = [&](int zp, int slot) {
+        if (!has_halo) return;
+        int zo[3];
+        zoffs(zp, zo);
+        const WallBits hb{wh.wx, wh.wy, zbits(zp)};
+        R hv;
+        if (node_solid<GEOM>(links, hxy[4] + zo[1], hb)) hv = R(-1);
+        else {
+            R sum = 0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) sum += pf_value<T, R>(pf_halo[i][tid]);
+            hv = psi_of(sum);
+        }
+        ring[slot][cell(hy + 1, hx)] = hv;
+    };
+    auto take_own = [&](int zp, int slot, R* v) {
+        if (!own_lane) return;
+        int zo[3];
+        zoffs(zp, zo);
+        const WallBits wb{wo.wx, wo.wy, zbits(zp)};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) v[i] = pf_value<T, R>(pf_own[i][tid]);
+        ring[slot][cell(ly + 1, lx)] =
+            node_solid<GEOM>(links, oxy[4] + zo[1], wb) ? R(-1) : psi_of(sum_q<Q, R>(v));
+    };
+
+    R cur[Q], nxt[Q];
+    own_psi(z0 - 1, 0, nxt);
+    halo_psi(z0 - 1, 0);
+    own_psi(z0, 1, cur);
+    halo_psi(z0, 1);
+    prefetch_halo(z0 + 1);
+    prefetch_own(z0 + 1);
+    // as in fused_tile_pf: after the Q stores of the previous plane, the wait for the
+    // prefetched plane leaves those stores in flight
+    bool stored = false;
+    for (int z = z0; z < z1; ++z) {
+        const int k = z - z0;
+        const int s0 = k & 3, s1 = (k + 1) & 3, s2 = (k + 2) & 3;
+        const bool more = z + 1 < z1;
+        if (stored) wait_vector_memory_but<Q>();
+        else wait_vector_memory();
+        take_halo(z + 1, s2);
+        wait_lds();
+        if (more) prefetch_halo(z + 2);
+        take_own(z + 1, s2, nxt);
+        wait_lds();
+        if (more) prefetch_own(z + 2);
+        barrier_lds();
+        const R psi0 = ring[s1][cell(ly + 1, lx)];
+        const bool fluid_node = active && !(psi0 < R(0));
+        stored = __any(fluid_node);
+        if (fluid_node) {
+            R pn[Q];
+#pragma unroll
+            for (int j = 0; j < Q; ++j) {
+                const int ez = vel_z(j);
+                const int sl = ez < 0 ? s0 : (ez > 0 ? s2 : s1);
+                pn[j] = ring[sl][cell(ly + 1 + vel_y(j), col(vel_x(j)))];
+            }
+            const NodeForce<R> nf = node_force<Q, R, GEOM != GEOM_NONE>(psi0, pn, P);
+            collide<Q, R>(cur, nf, P);
+            const unsigned nb = (unsigned)(oxy[4] + z * nxy) * (unsigned)sizeof(T);
+            if constexpr (NTS) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    st_off_nt(fout, nb + (unsigned)i * pst, static_cast<T>(cur[i]));
+            } else {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) st_off(fout, nb + (unsigned)i * pst, static_cast<T>(cur[i]));
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
+    }
+}
+
+// Batched step with row tiles of run-time width (fused_tile_rows): as k_step_fused_batch.
+template <int Q, typename T, int GEOM, int NT, bool NTS>
+__global__ __launch_bounds__(NT) void k_step_fused_batch_rows(const DomainDesc<T>* __restrict__ d,
+                                                             int ndom, int remap) {
+    const int b = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    int lo = 0, hi = ndom - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].block0 <= b) lo = mid; else hi = mid - 1;
+    }
+    const DomainDesc<T>& D = d[lo];
+    fused_tile_rows<Q, T, GEOM, NT, NTS>(D.fin, D.fout, D.links, D.g, D.P, b - D.block0, D.rows,
+                                         D.nty, D.zc);
 }
 
 }  // namespace lbmk

@@ -37,15 +37,17 @@ def _make(L, w, storage):
 
 
 @pytest.mark.parametrize("variant", ["plain", "plain_nt", "prefetch", "prefetch_nt", "tiles32x8",
-                                     "dispatch_order"])
+                                     "dispatch_order", "rows", "rows_nt"])
 @pytest.mark.parametrize("storage", ["fp32", "fp64"])
 def test_batch_equals_individual_steps(L, monkeypatch, storage, variant):
     """Batched launches (default plain 64x4 tiles in XCD order, prefetching tiles, 32x8
-    tiles, dispatch order; plain stores, the default for these unaligned rows, or
-    nontemporal ones) give each member exactly the populations of its own single-lattice
-    steps."""
+    tiles, dispatch order, row tiles of run-time width (4-byte storage; FP64 keeps the
+    64x4 tiles); plain stores, the default for these unaligned rows, or nontemporal ones)
+    give each member exactly the populations of its own single-lattice steps."""
     if variant.startswith("prefetch"):
         monkeypatch.setenv("LBM_BATCH_PF", "1")
+    if variant.startswith("rows"):
+        monkeypatch.setenv("LBM_BATCH_ROWS", "1")
     if variant.endswith("_nt"):
         monkeypatch.setenv("LBM_BATCH_NT", "1")
     if variant == "dispatch_order":
@@ -114,13 +116,17 @@ def test_serving_results_same_alone_and_in_the_mix(L):
         assert r["finite"]
 
 
-@pytest.mark.parametrize("storage", ["fp64", "fp32"])
-def test_batch_members_match_the_oracle(L, storage):
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp32_rows"])
+def test_batch_members_match_the_oracle(L, monkeypatch, storage):
     """Every member of a batch against the FP64 oracle (not only against its own single-
     lattice run): three small lattices (walls, a cylinder with wetting, kappa, a ragged
     shape) from seeded random states, one batch run of 10 steps. FP64 populations to 1e-13
-    absolute; FP32 shifted storage to 1e-5 relative in rho and 1e-4 absolute in u."""
+    absolute; FP32 shifted storage (64x4 tiles, or row tiles of run-time width) to 1e-5
+    relative in rho and 1e-4 absolute in u."""
     from oracle import lbm as olbm
+    if storage == "fp32_rows":
+        monkeypatch.setenv("LBM_BATCH_ROWS", "1")
+        storage = "fp32"
     from tests.helpers import abs_err, oracle_params, rel_err
     ws = [si.Workload("a", 19, 20, 16, 12, T_over_Tc=0.6, walls=("z_lo", "z_hi"), G_ads=0.1,
                       kappa=0.3, nu=0.05),
