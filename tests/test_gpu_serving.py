@@ -96,6 +96,44 @@ def test_batch_rejects_bad_arguments(L):
     b64.close()
 
 
+def test_row_tiles_on_extreme_widths(L, monkeypatch):
+    """Row tiles of run-time width at the edges of their range, bitwise against each
+    member's own single-lattice steps: the widest eligible member (384: two rows per
+    workgroup, a ragged last tile), 1- and 2-node widths (hundreds of rows, lanes wrapping
+    onto themselves in x), a single row (both halo rows are the row itself), and 7 x 130
+    between y walls (109 rows and a ragged tile whose surplus lanes wrap past the wall)."""
+    monkeypatch.setenv("LBM_BATCH_ROWS", "1")
+    ws = [si.Workload("w384", 19, 384, 5, 6, T_over_Tc=0.7, walls=("z_lo", "z_hi"),
+                      G_ads=0.1, nu=0.05),
+          si.Workload("w1", 19, 1, 9, 4, T_over_Tc=0.6, nu=0.08),
+          si.Workload("w2", 19, 2, 1, 3, T_over_Tc=0.7, walls=("z_lo",), kappa=0.3),
+          si.Workload("w7", 19, 7, 130, 5, T_over_Tc=0.6, walls=("y_lo", "y_hi"),
+                      G_ads=-0.1, nu=0.1)]
+
+    def make(w, k):
+        rv, _ = maxwell(w)
+        lat = L.Lattice(gpu_params(w, "fp32", rho_ref=rv))
+        rho, u = si.random_fields(w.shape, seed=60 + k, rho_lo=0.05, rho_hi=0.4)
+        lat.init_fields(rho, u)
+        return lat
+
+    alone = [make(w, k) for k, w in enumerate(ws)]
+    mixed = [make(w, k) for k, w in enumerate(ws)]
+    for lat in alone:
+        lat.step(8)
+    b = L.lbm_batch_create([m.ctx for m in mixed], 4)
+    try:
+        L.lbm_batch_run(b, 2)
+    finally:
+        L.lbm_batch_destroy(b)
+    for a, m, w in zip(alone, mixed, ws):
+        fa, fm = a.get_populations(), m.get_populations()
+        print(f"row tiles {w.name}: max |alone - batched| = {float(np.max(np.abs(fa - fm))):.3e}")
+        assert np.array_equal(fa, fm), w.name
+    for lat in alone + mixed:
+        lat.close()
+
+
 def test_serving_results_same_alone_and_in_the_mix(L):
     """A compressed trace of 8 impact requests through the continuous-batching loop and
     through the one-at-a-time loop (same FP32 storage): every request's result (spreading
