@@ -218,6 +218,41 @@ def static32_oracle():
     return w, P, f0, f100, dens
 
 
+@pytest.fixture(scope="module")
+def static32_oracle_200(static32_oracle):
+    """The same droplet at the configuration's own length (200 steps)."""
+    w, P, f0, f100, dens = static32_oracle
+    return w, P, olbm.run(f100, P, 100), dens
+
+
+@KERNELS
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_static_droplet_configuration_200_steps(L, static32_oracle_200, storage, kernel):
+    """The 32^3 static-droplet configuration as specified (CS at 0.7 T_c, R = 8, tanh width
+    5, unit non-viscous rates, nu = 0.1, 200 steps), reporting what it asks for: the density
+    and pressure fields and the total mass, against the oracle. FP64: rho 1e-12 relative,
+    p 1e-12 of its largest magnitude, mass 1e-13 relative; FP32 shifted storage (rho_ref =
+    vapour density): rho 1e-5 relative, p 1e-5 of its largest magnitude, mass 1e-6."""
+    w, P, f200, (rv, rl) = static32_oracle_200
+    rho_ref = rv if storage == "fp32" else 0.0
+    with L.Lattice(gpu_params(w, storage, rho_ref=rho_ref,
+                              step_kernel=kernel_code(L, kernel))) as lat:
+        cx, cy, cz = w.droplet_centre()
+        lat.init_droplet(cx, cy, cz, w.R, w.W, rl, rv)
+        lat.step(w.steps)
+        mom = lat.moments(want=("rho", "p", "totals"))
+        mass = mom["totals"][0]
+    ro, _, po, _ = olbm.moments(f200, P)
+    mass_o = float(ro.sum())
+    e_rho = rel_err(mom["rho"], ro)
+    e_p = float(np.max(np.abs(mom["p"] - po)) / np.max(np.abs(po)))
+    e_m = abs(mass - mass_o) / mass_o
+    print(f"{storage} 32^3 200 steps ({kernel}): rho rel {e_rho:.2e}, p {e_p:.2e}, "
+          f"mass {e_m:.2e} (oracle mass {mass_o:.10f})")
+    bars = (1e-12, 1e-12, 1e-13) if storage == "fp64" else (1e-5, 1e-5, 1e-6)
+    assert e_rho < bars[0] and e_p < bars[1] and e_m < bars[2]
+
+
 @KERNELS
 def test_fp64_static_droplet_100_steps(L, static32_oracle, kernel):
     w, P, f0, f100, (rv, rl) = static32_oracle
