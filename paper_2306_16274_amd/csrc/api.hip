@@ -48,7 +48,7 @@ static double* scratch_of(int device) {
 }
 
 static int default_fused_cfg(const lbm_ctx* c) {
-    return fused_cfg_for(c->p.nx, (int)c->elem, c->Q, c->addr64);
+    return fused_cfg_for(c->p.nx, (int)c->elem, c->Q, c->addr64, c->p.cylinder != 0);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -427,7 +427,7 @@ extern "C" lbm_status lbm_fused_plan(const lbm_params* p, int32_t cus, lbm_fused
     if (st != LBM_OK) return st;
     const int elem = (int)storage_bytes(p->storage), Q = p->lattice;
     const bool addr64 = needs_addr64(*p);
-    const int cfg = fused_cfg_for(p->nx, elem, Q, addr64);
+    const int cfg = fused_cfg_for(p->nx, elem, Q, addr64, p->cylinder != 0);
     const FusedCfg& f = kFusedCfgs[cfg];
     const FusedPlan pl = fused_plan(*p, elem, cfg, cus);
     out->config = cfg;
@@ -439,6 +439,7 @@ extern "C" lbm_status lbm_fused_plan(const lbm_params* p, int32_t cus, lbm_fused
     out->xcd_order = pl.remap;
     out->hints = addr64 ? (pl.hints & ~kHintNtStore) : pl.hints;
     out->addr64 = addr64 ? 1 : 0;
+    out->z_first = pl.zlo;
     out->workgroups = pl.workgroups;
     return LBM_OK;
 }

@@ -133,11 +133,15 @@ constexpr int default_fused_hints(const FusedCfg& c, int elem_bytes) {
 // 43-45 vs 30.7), D3Q27 plain (320 x 256 x 192 FP32 19.3 vs 15.5, 19.3 prefetching, which
 // spills; FP16 28.1 vs 21.5); FP64 takes 64x4 tiles (32x8: 12.3-12.7 vs 9.4 at 384^2 x 160,
 // 6.7-7.1 vs 5.4-5.6 for D3Q27 at 320 x 256 x 192: 640 or 768 threads leave too few VGPRs).
-constexpr int default_fused_cfg_index(int nx, int elem_bytes, int Q) {
+// D3Q27 on a solid mask at width 320 (the cylinder workload, 320 x 256 x 192, walls and a
+// cylinder with wetting): prefetching 320x2 tiles, FP32 1.02 vs 1.22-1.26 ms plain, FP16 0.92
+// vs 0.99-1.03 (the masked form holds 161 VGPRs without spills; between plain walls it spills).
+constexpr int default_fused_cfg_index(int nx, int elem_bytes, int Q, bool mask = false) {
     return (nx == 320 || nx == 384)
                ? (elem_bytes == 8 ? 9
                   : Q == 19 && fused_pf_lds_bytes(Q, nx, 2) <= kLdsBytesPerCU ? (nx == 320 ? 6 : 8)
-                  : (nx == 320 ? 5 : 7))
+                  : nx == 320 ? (mask && fused_pf_lds_bytes(Q, nx, 2) <= kLdsBytesPerCU ? 6 : 5)
+                  : 7)
          : nx != 256 ? (elem_bytes == 4 ? 10 : 9)
          : elem_bytes == 8 ? (Q == 27 && fused_pf64_lds_bytes(Q, 256, 2) <= kLdsBytesPerCU ? 4 : 1)
          : elem_bytes == 4 ? (fused_pf_lds_bytes(Q, 256, 4) <= kLdsBytesPerCU ? 3
@@ -245,6 +249,49 @@ __device__ __forceinline__ R sum_q(const R* v) {
     return s;
 }
 
+// Planes z0 .. z1 - 1 of z-chunk iz: chunk 0 holds g.zlo planes (zc when g.zlo is 0), the
+// others zc, the last the rest.
+__device__ __forceinline__ void chunk_range(const Grid& g, int iz, int zc, int& z0, int& z1) {
+    const int zl = g.zlo > 0 ? g.zlo : zc;
+    z0 = iz == 0 ? 0 : zl + (iz - 1) * zc;
+    z1 = min(zl + iz * zc, g.nz);
+}
+
+// LDS of one tile shape, shared by the geometry forms of that shape: a kernel that runs the
+// solid-free form of its tile on some z-chunks (see solid_free) then holds one copy of the
+// tile's buffers, not one per form.
+template <typename R, int LY, int LX>
+struct RingLds { R ring[4][LY][LX]; };
+template <typename R, int LY, int LX>
+__device__ __forceinline__ RingLds<R, LY, LX>& ring_lds() {
+    __shared__ RingLds<R, LY, LX> s;
+    return s;
+}
+template <typename S, int Q, int LY, int LX, int NT, int H>
+struct PfLds {
+    float ring[4][LY][LX];
+    S own[Q][NT];
+    S halo[Q][H];
+};
+template <typename S, int Q, int LY, int LX, int NT, int H>
+__device__ __forceinline__ PfLds<S, Q, LY, LX, NT, H>& pf_lds() {
+    __shared__ PfLds<S, Q, LY, LX, NT, H> s;
+    return s;
+}
+
+// solid_free: bit iz is set when z-chunk iz (planes z0 .. z1-1) and the two planes either
+// side of it hold no solid node (computed on the host from the walls and the cylinder).
+// Every node such a chunk collides then has only fluid nodes within two planes, so the pulls
+// need no bounce-back, every psi it reads is a fluid node's, and the solid and wetting terms
+// vanish: the form of the tile for a lattice without solid nodes gives the same values for
+// those nodes (up to the sign of exact zeros). Walled and cylinder lattices of 2- and 4-byte
+// storage run that form on such chunks; FP64 tiles always take the general form.
+template <typename T, int GEOM>
+__device__ __forceinline__ bool run_solid_free(uint64_t solid_free, int iz) {
+    if constexpr (GEOM == GEOM_NONE || sizeof(T) == 8) return false;
+    else return iz < 64 && ((solid_free >> iz) & 1ull) != 0;
+}
+
 // FULLX: the tile spans the whole x extent (TX == nx); x wraps inside the tile and the
 // halo is just the rows y0-1 and y0+TY (H = 2 TX, one halo node per thread when TY = 2).
 // One tile (workgroup) of the fused step: tile index t of a domain with ntx x nty tiles
@@ -254,19 +301,26 @@ template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX, bool NTS, boo
 __device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restrict__ fout,
                                            const uint32_t* __restrict__ links, const Grid& g,
                                            const Phys<typename Arith<T>::type>& P,
-                                           int t, int ntx, int nty, int zc, int hints) {
+                                           int t, int ntx, int nty, int zc, int hints,
+                                           uint64_t solid_free = 0) {
     using R = typename Arith<T>::type;
     constexpr int LX = FULLX ? TX : TX + 2, LY = TY + 2;
     constexpr int OX = FULLX ? 0 : 1;                 // LDS column of tile column 0
     constexpr int H = FULLX ? 2 * TX : 2 * (TX + TY) + 4;
     static_assert(H <= TX * TY, "halo larger than the workgroup");
-    __shared__ R ring[4][LY][LX];
+    if (run_solid_free<T, GEOM>(solid_free, t / (ntx * nty))) {
+        fused_tile<Q, T, GEOM_NONE, TX, TY, FULLX, NTS, WIDE>(fin, fout, links, g, P, t, ntx, nty,
+                                                              zc, hints);
+        return;
+    }
+    auto& ring = ring_lds<R, LY, LX>().ring;
 
     const int ix = t % ntx; t /= ntx;
     const int iy = t % nty;
     const int iz = t / nty;
-    const int x0 = ix * TX, y0 = iy * TY, z0 = iz * zc;
-    const int z1 = min(z0 + zc, g.nz);
+    const int x0 = ix * TX, y0 = iy * TY;
+    int z0, z1;
+    chunk_range(g, iz, zc, z0, z1);
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
     const int x = x0 + lx, y = y0 + ly;
@@ -460,7 +514,7 @@ template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX, bool NTS>
 __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __restrict__ fout,
                                               const uint32_t* __restrict__ links, const Grid& g,
                                               const Phys<float>& P, int t, int ntx, int nty,
-                                              int zc, int hints) {
+                                              int zc, int hints, uint64_t solid_free = 0) {
     static_assert(sizeof(T) == 4 || sizeof(T) == 2, "the LDS prefetch moves 2- or 4-byte elements");
     using R = float;
     using S = typename PfSlot<T>::type;
@@ -471,11 +525,17 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
     static_assert(H <= NT && (!FULLX || TX % 64 == 0),
                   "halo larger than the tile, or full rows not whole wavefronts");
     static_assert(fused_pf_lds_bytes(Q, TX, TY, FULLX) <= kLdsBytesPerCU, "tile does not fit in LDS");
-    __shared__ R ring[4][TY + 2][LX];
-    __shared__ S pf_own[Q][NT];
+    if (run_solid_free<T, GEOM>(solid_free, t / (ntx * nty))) {
+        fused_tile_pf<Q, T, GEOM_NONE, TX, TY, FULLX, NTS>(fin, fout, links, g, P, t, ntx, nty, zc,
+                                                           hints);
+        return;
+    }
     // the halo buffer holds H cells; the DMA of the last, partly used wavefront writes only
     // its active lanes
-    __shared__ S pf_halo[Q][H];
+    auto& lds = pf_lds<S, Q, TY + 2, LX, NT, H>();
+    auto& ring = lds.ring;
+    auto& pf_own = lds.own;
+    auto& pf_halo = lds.halo;
     // this wavefront's slots of population 0 in the two buffers (scalars)
     const uint32_t own_lds = lds_addr(&pf_own[0][(threadIdx.x >> 6) * 64]);
     const uint32_t halo_lds = lds_addr(&pf_halo[0][(threadIdx.x >> 6) * 64]);
@@ -483,8 +543,9 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
     const int ix = t % ntx; t /= ntx;
     const int iy = t % nty;
     const int iz = t / nty;
-    const int x0 = ix * TX, y0 = iy * TY, z0 = iz * zc;
-    const int z1 = min(z0 + zc, g.nz);
+    const int x0 = ix * TX, y0 = iy * TY;
+    int z0, z1;
+    chunk_range(g, iz, zc, z0, z1);
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
     const int x = x0 + lx, y = y0 + ly;
@@ -707,8 +768,9 @@ __device__ __forceinline__ void fused_tile_pf64(const double* __restrict__ fin,
 
     const int iy = t % nty;
     const int iz = t / nty;
-    const int y0 = iy * TY, z0 = iz * zc;
-    const int z1 = min(z0 + zc, g.nz);
+    const int y0 = iy * TY;
+    int z0, z1;
+    chunk_range(g, iz, zc, z0, z1);
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
     const int x = lx, y = y0 + ly;
@@ -848,10 +910,11 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_pf(const T* __restrict__
                                                           T* __restrict__ fout,
                                                           const uint32_t* __restrict__ links,
                                                           Grid g, Phys<float> P, int zc,
-                                                          int remap, int hints) {
+                                                          int remap, int hints,
+                                                          uint64_t solid_free) {
     const int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     fused_tile_pf<Q, T, GEOM, TX, TY, true, NTS>(fin, fout, links, g, P, t, 1,
-                                                 (g.ny + TY - 1) / TY, zc, hints);
+                                                 (g.ny + TY - 1) / TY, zc, hints, solid_free);
 }
 
 // Single domain. remap != 0: map workgroups to tiles so that each XCD gets a contiguous
@@ -862,9 +925,10 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(const T* __restrict__ fi
                                                        const uint32_t* __restrict__ links,
                                                        Grid g, Phys<typename Arith<T>::type> P,
                                                        int ntx, int nty, int zc, int remap,
-                                                       int hints) {
+                                                       int hints, uint64_t solid_free) {
     const int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    fused_tile<Q, T, GEOM, TX, TY, FULLX, NTS, WIDE>(fin, fout, links, g, P, t, ntx, nty, zc, hints);
+    fused_tile<Q, T, GEOM, TX, TY, FULLX, NTS, WIDE>(fin, fout, links, g, P, t, ntx, nty, zc, hints,
+                                                     solid_free);
 }
 
 // One domain of a batched step: its buffers, geometry, physics and the first workgroup
@@ -878,6 +942,7 @@ struct DomainDesc {
     Phys<typename Arith<T>::type> P;
     int ntx, nty, zc, block0;
     int rows;                  // rows per tile of the row-tile kernel (k_step_fused_batch_rows)
+    uint64_t solid_free;       // z-chunks without a solid node within two planes (fused_tile)
 };
 
 // Many independent lattices advanced by one launch: workgroup b (after the XCD-contiguous
@@ -894,7 +959,7 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_batch(const DomainDesc<T
     }
     const DomainDesc<T>& D = d[lo];
     fused_tile<Q, T, GEOM, TX, TY, false, NTS>(D.fin, D.fout, D.links, D.g, D.P, b - D.block0,
-                                               D.ntx, D.nty, D.zc, 0);
+                                               D.ntx, D.nty, D.zc, 0, D.solid_free);
 }
 
 // Batched step with prefetching tiles (4-byte storage): as k_step_fused_batch.
@@ -909,7 +974,7 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_batch_pf(const DomainDes
     }
     const DomainDesc<T>& D = d[lo];
     fused_tile_pf<Q, T, GEOM, TX, TY, false, NTS>(D.fin, D.fout, D.links, D.g, D.P, b - D.block0,
-                                                  D.ntx, D.nty, D.zc, 0);
+                                                  D.ntx, D.nty, D.zc, 0, D.solid_free);
 }
 
 
@@ -926,22 +991,28 @@ template <int Q, typename T, int GEOM, int NT, bool NTS>
 __device__ __forceinline__ void fused_tile_rows(const T* __restrict__ fin, T* __restrict__ fout,
                                                 const uint32_t* __restrict__ links, const Grid& g,
                                                 const Phys<float>& P, int t, int rows, int nty,
-                                                int zc) {
+                                                int zc, uint64_t solid_free = 0) {
     static_assert(sizeof(T) == 4 || sizeof(T) == 2, "the LDS prefetch moves 2- or 4-byte elements");
     static_assert(NT % 64 == 0, "whole wavefronts");
     using R = float;
     using S = typename PfSlot<T>::type;
-    __shared__ R ring[4][2 * NT];
-    __shared__ S pf_own[Q][NT];
-    __shared__ S pf_halo[Q][NT];
+    if (run_solid_free<T, GEOM>(solid_free, t / nty)) {
+        fused_tile_rows<Q, T, GEOM_NONE, NT, NTS>(fin, fout, links, g, P, t, rows, nty, zc);
+        return;
+    }
+    auto& lds = pf_lds<S, Q, 1, 2 * NT, NT, NT>();
+    auto& ring_rows = lds.ring;
+    auto& pf_own = lds.own;
+    auto& pf_halo = lds.halo;
     const uint32_t own_lds = lds_addr(&pf_own[0][(threadIdx.x >> 6) * 64]);
     const uint32_t halo_lds = lds_addr(&pf_halo[0][(threadIdx.x >> 6) * 64]);
 
     const int L = g.nx;
     const int iy = t % nty;
     const int iz = t / nty;
-    const int y0 = iy * rows, z0 = iz * zc;
-    const int z1 = min(z0 + zc, g.nz);
+    const int y0 = iy * rows;
+    int z0, z1;
+    chunk_range(g, iz, zc, z0, z1);
     const int tid = threadIdx.x;
     // lanes without a node take node 0's column and row (valid addresses; never stored, and
     // they write no ring cell)
@@ -991,7 +1062,7 @@ __device__ __forceinline__ void fused_tile_rows(const T* __restrict__ fin, T* __
         const WallBits wb{wo.wx, wo.wy, zbits(zp)};
         const bool sld = node_solid<GEOM>(links, oxy[4] + zo[1], wb);
         pull_loads<Q, T, R, GEOM>(fin, links, oxy, zo, wb, pst, v);
-        if (own_lane) ring[slot][cell(ly + 1, lx)] = sld ? R(-1) : psi_of(sum_q<Q, R>(v));
+        if (own_lane) ring_rows[slot][0][cell(ly + 1, lx)] = sld ? R(-1) : psi_of(sum_q<Q, R>(v));
     };
     auto halo_psi = [&](int zp, int slot) {
         if (!has_halo) return;
@@ -1005,7 +1076,7 @@ __device__ __forceinline__ void fused_tile_rows(const T* __restrict__ fin, T* __
             pull_loads<Q, T, R, GEOM>(fin, links, hxy, zo, wb, pst, v);
             hv = psi_of(sum_q<Q, R>(v));
         }
-        ring[slot][cell(hy + 1, hx)] = hv;
+        ring_rows[slot][0][cell(hy + 1, hx)] = hv;
     };
     // asynchronous pulls of plane zp into the LDS buffers (lanes with a node / a halo node)
     auto prefetch_own = [&](int zp) {
@@ -1051,7 +1122,7 @@ __device__ __forceinline__ void fused_tile_rows(const T* __restrict__ fin, T* __
             for (int i = 0; i < Q; ++i) sum += pf_value<T, R>(pf_halo[i][tid]);
             hv = psi_of(sum);
         }
-        ring[slot][cell(hy + 1, hx)] = hv;
+        ring_rows[slot][0][cell(hy + 1, hx)] = hv;
     };
     auto take_own = [&](int zp, int slot, R* v) {
         if (!own_lane) return;
@@ -1060,7 +1131,7 @@ __device__ __forceinline__ void fused_tile_rows(const T* __restrict__ fin, T* __
         const WallBits wb{wo.wx, wo.wy, zbits(zp)};
 #pragma unroll
         for (int i = 0; i < Q; ++i) v[i] = pf_value<T, R>(pf_own[i][tid]);
-        ring[slot][cell(ly + 1, lx)] =
+        ring_rows[slot][0][cell(ly + 1, lx)] =
             node_solid<GEOM>(links, oxy[4] + zo[1], wb) ? R(-1) : psi_of(sum_q<Q, R>(v));
     };
 
@@ -1087,7 +1158,7 @@ __device__ __forceinline__ void fused_tile_rows(const T* __restrict__ fin, T* __
         wait_lds();
         if (more) prefetch_own(z + 2);
         barrier_lds();
-        const R psi0 = ring[s1][cell(ly + 1, lx)];
+        const R psi0 = ring_rows[s1][0][cell(ly + 1, lx)];
         const bool fluid_node = active && !(psi0 < R(0));
         stored = __any(fluid_node);
         if (fluid_node) {
@@ -1096,7 +1167,7 @@ __device__ __forceinline__ void fused_tile_rows(const T* __restrict__ fin, T* __
             for (int j = 0; j < Q; ++j) {
                 const int ez = vel_z(j);
                 const int sl = ez < 0 ? s0 : (ez > 0 ? s2 : s1);
-                pn[j] = ring[sl][cell(ly + 1 + vel_y(j), col(vel_x(j)))];
+                pn[j] = ring_rows[sl][0][cell(ly + 1 + vel_y(j), col(vel_x(j)))];
             }
             const NodeForce<R> nf = node_force<Q, R, GEOM != GEOM_NONE>(psi0, pn, P);
             collide<Q, R>(cur, nf, P);
@@ -1127,7 +1198,7 @@ __global__ __launch_bounds__(NT) void k_step_fused_batch_rows(const DomainDesc<T
     }
     const DomainDesc<T>& D = d[lo];
     fused_tile_rows<Q, T, GEOM, NT, NTS>(D.fin, D.fout, D.links, D.g, D.P, b - D.block0, D.rows,
-                                         D.nty, D.zc);
+                                         D.nty, D.zc, D.solid_free);
 }
 
 }  // namespace lbmk

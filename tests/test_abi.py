@@ -134,11 +134,15 @@ def test_create_rejects_invalid_parameters_before_touching_the_device(changes, m
     assert message in str(ei.value), str(ei.value)
 
 
-def _plan_params(lbm, nx, ny, nz, storage=1, Q=19, cylinder=False):
+def _plan_params(lbm, nx, ny, nz, geometry=None, storage=1, Q=19):
+    """lbm_params of a lattice for the plan tests; geometry None (periodic), "cylinder" (an
+    x-aligned cylinder) or "zwalls" (walls at z = 0 and z = nz - 1)."""
     p = lbm.lbm_params_default()
     p.nx, p.ny, p.nz, p.storage, p.lattice = nx, ny, nz, storage, Q
-    if cylinder:
+    if geometry == "cylinder":
         p.cylinder, p.cyl_y, p.cyl_z, p.cyl_r = 1, ny / 2.0, 10.0, 8.0
+    if geometry == "zwalls":
+        p.bc[2][0] = p.bc[2][1] = lbm.LBM_BC_WALL
     return p
 
 
@@ -162,6 +166,14 @@ def _plan_params(lbm, nx, ny, nz, storage=1, Q=19, cylinder=False):
     # D3Q27 at 384 wide does not fit the prefetch buffers: plain 384x2
     ((384, 256, 64), 1, 27, dict(config=7, prefetch=0)),
     ((320, 256, 192), 1, 27, dict(config=5, tile_x=320, prefetch=0, z_chunk=96)),
+    # ... but on a cylinder mask the prefetching 320x2 tiles (FP32 and FP16)
+    ((320, 256, 192, "cylinder"), 1, 27, dict(config=6, tile_x=320, prefetch=1, z_chunk=96)),
+    ((320, 256, 192, "cylinder"), 2, 27, dict(config=6, prefetch=1)),
+    # between walls along z: shorter walled end chunks (the general form), longer interior
+    # ones (the solid-free form), one round of 256 workgroups
+    ((256, 256, 256, "zwalls"), 1, 19, dict(config=3, z_first=51, z_chunk=77, workgroups=256)),
+    ((256, 256, 256, "zwalls"), 2, 19, dict(config=3, z_first=43, z_chunk=85, workgroups=256)),
+    ((256, 256, 256, "zwalls"), 0, 19, dict(config=1, z_first=128, z_chunk=128)),
     # other widths: 64x8 tiles for 4-byte storage, 64x4 otherwise, 16-plane chunks
     ((300, 300, 250), 1, 19, dict(config=10, tile_x=64, tile_y=8, full_rows=0, z_chunk=16, hints=0)),
     ((300, 300, 250), 2, 27, dict(config=9, tile_x=64, tile_y=4, z_chunk=16)),
