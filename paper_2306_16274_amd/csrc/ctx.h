@@ -155,11 +155,8 @@ inline bool fused_prefetch_fits(const FusedCfg& f, int Q, int elem) {
 // no solid node run the arithmetic of a lattice without solid nodes (2- and 4-byte storage).
 // LBM_SOLID_FREE=0 turns it off (tuning).
 inline bool solid_free_enabled() {
-    static const bool on = [] {
-        const char* e = getenv("LBM_SOLID_FREE");
-        return !e || atoi(e) != 0;
-    }();
-    return on;
+    const char* e = getenv("LBM_SOLID_FREE");
+    return !e || atoi(e) != 0;
 }
 
 // Z-chunk layout of the fused step: chunk 0 holds zlo planes, the others zc, the last the
