@@ -254,8 +254,6 @@ typedef struct {
     int32_t xcd_order;    /* 1: tiles mapped to XCDs in contiguous ranges (LBM_FUSED_REMAP) */
     int32_t hints;        /* bit 0: nontemporal stores; bit 1: nontemporal interior loads  */
     int32_t addr64;       /* 1: 64-bit byte offsets (population buffer of 4 GiB or more)    */
-    int32_t z_first;      /* planes of the first z-chunk (the last holds the rest); differs
-                             from z_chunk when walls along z shorten the walled end chunks   */
     int64_t workgroups;   /* workgroups of one time step                                    */
 } lbm_fused_plan_t;
 lbm_status lbm_fused_plan(const lbm_params* p, int32_t cus, lbm_fused_plan_t* out);

@@ -439,7 +439,6 @@ extern "C" lbm_status lbm_fused_plan(const lbm_params* p, int32_t cus, lbm_fused
     out->xcd_order = pl.remap;
     out->hints = addr64 ? (pl.hints & ~kHintNtStore) : pl.hints;
     out->addr64 = addr64 ? 1 : 0;
-    out->z_first = pl.zlo;
     out->workgroups = pl.workgroups;
     return LBM_OK;
 }

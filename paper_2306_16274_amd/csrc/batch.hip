@@ -117,8 +117,7 @@ static lbm_status build_tables(lbm_batch* b) {
         int zc = kBatchZC;
         if (const char* e = getenv("LBM_BATCH_ZC")) zc = std::max(1, atoi(e));    // tuning override
         zc = std::min(zc, c->p.nz);
-        const ZChunks zk = batch_zchunks(c->p, zc);
-        const long long nb = (long long)ntx * nty * zk.n;
+        const long long nb = (long long)ntx * nty * ((c->p.nz + zc - 1) / zc);
         const Phys<R>& P = phys_of<R>(c);
         for (int par = 0; par < 2; ++par) {
             DomainDesc<T> d{};
@@ -126,11 +125,9 @@ static lbm_status build_tables(lbm_batch* b) {
             d.fout = (T*)c->f[(c->cur + par + 1) & 1];
             d.links = c->links;
             d.g = grid_of(c);
-            d.g.zlo = zk.zlo;
             d.P = P;
             d.ntx = ntx; d.nty = nty; d.zc = zc; d.block0 = (int)block0;
             d.rows = rows;
-            d.solid_free = solid_free_chunks(c->p, zk);
             t[par].push_back(d);
         }
         block0 += nb;

@@ -24,7 +24,7 @@ struct Grid {
     int nx, ny, nz;
     int walls;                // solid layers: bit 2a = axis a low face, bit 2a+1 = high face
     long long stride;         // elements between population planes
-    int zlo;                  // fused step: planes of the first z-chunk (0: as the others)
+    int sf0, sf1;             // fused step: planes [sf0, sf1) may run the solid-free form
 };
 
 // Indices of x + e_j for all j (periodic wrap on every axis).

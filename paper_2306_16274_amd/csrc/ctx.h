@@ -103,11 +103,48 @@ inline Launch node_launch(const lbm_ctx* c) {
 }
 inline long long nblocks(const Launch& L) { return (long long)L.grid.x * L.grid.y * L.grid.z; }
 
+// Solid-free form of the fused tiles (fused_segments in fused.h), 2- and 4-byte storage:
+// planes z whose planes z - 2 .. z + 2 hold no solid node run the arithmetic of a lattice
+// without solid nodes. LBM_SOLID_FREE=0 turns it off (tuning).
+inline bool solid_free_enabled() {
+    const char* e = getenv("LBM_SOLID_FREE");
+    return !e || atoi(e) != 0;
+}
+
+// The longest run [sf0, sf1) of planes z whose planes z - 2 .. z + 2 hold no solid node
+// (sf0 = sf1 = 0 if none). Walls along x or y put solid nodes in every plane; a wall along z
+// is the plane 0 or nz - 1; a cylinder along x fills the planes cyl_z - cyl_r .. cyl_z + cyl_r
+// (taken one plane wider either side). A lattice without walls or cylinder is periodic in z:
+// every plane qualifies.
+inline void solid_free_range(const lbm_params& p, int& sf0, int& sf1) {
+    sf0 = sf1 = 0;
+    if (!solid_free_enabled()) return;
+    for (int a = 0; a < 2; ++a)
+        if (p.bc[a][0] == LBM_BC_WALL || p.bc[a][1] == LBM_BC_WALL) return;
+    const int nz = p.nz;
+    auto solid_plane = [&](int z) {
+        if (z < 0 || z >= nz) z = ((z % nz) + nz) % nz;
+        if (p.bc[2][0] == LBM_BC_WALL && z == 0) return true;
+        if (p.bc[2][1] == LBM_BC_WALL && z == nz - 1) return true;
+        return p.cylinder != 0 && z >= std::floor(p.cyl_z - p.cyl_r) - 1 &&
+               z <= std::ceil(p.cyl_z + p.cyl_r) + 1;
+    };
+    int run0 = 0;
+    for (int z = 0; z <= nz; ++z) {
+        bool clear = z < nz;
+        for (int d = -2; d <= 2 && clear; ++d) clear = !solid_plane(z + d);
+        if (!clear) {
+            if (z - run0 > sf1 - sf0) { sf0 = run0; sf1 = z; }
+            run0 = z + 1;
+        }
+    }
+}
+
 inline Grid grid_of(const lbm_ctx* c) {
     Grid g;
     g.nx = c->p.nx; g.ny = c->p.ny; g.nz = c->p.nz; g.stride = c->stride;
     g.walls = 0;
-    g.zlo = 0;
+    solid_free_range(c->p, g.sf0, g.sf1);
     for (int a = 0; a < 3; ++a)
         for (int s = 0; s < 2; ++s)
             if (c->p.bc[a][s] == LBM_BC_WALL) g.walls |= 1 << (2 * a + s);
@@ -151,100 +188,10 @@ inline bool fused_prefetch_fits(const FusedCfg& f, int Q, int elem) {
     return fused_pf_lds_bytes(Q, f.tx, f.ty) <= kLdsBytesPerCU;
 }
 
-// Solid-free form of the fused tiles (fused.h): z-chunks whose planes z0 - 2 .. z1 + 1 hold
-// no solid node run the arithmetic of a lattice without solid nodes (2- and 4-byte storage).
-// LBM_SOLID_FREE=0 turns it off (tuning).
-inline bool solid_free_enabled() {
-    const char* e = getenv("LBM_SOLID_FREE");
-    return !e || atoi(e) != 0;
-}
-
-// Z-chunk layout of the fused step: chunk 0 holds zlo planes, the others zc, the last the
-// rest (zlo == zc: uniform chunks); n chunks.
-struct ZChunks { int zlo, zc, n; };
-inline ZChunks zchunks_of(int nz, int zlo, int zc) {
-    return {zlo, zc, nz <= zlo ? 1 : 1 + (nz - zlo + zc - 1) / zc};
-}
-
-// Whether the solid nodes of a lattice are the wall planes z = 0 and/or z = nz - 1 only.
-inline bool z_walls_only(const lbm_params& p) {
-    if (p.cylinder) return false;
-    for (int a = 0; a < 2; ++a)
-        if (p.bc[a][0] == LBM_BC_WALL || p.bc[a][1] == LBM_BC_WALL) return false;
-    return p.bc[2][0] == LBM_BC_WALL || p.bc[2][1] == LBM_BC_WALL;
-}
-
-// Cost of a plane in the general form of a tile relative to the solid-free form, measured on
-// lattices between z walls against periodic ones (ms per step): 256x4 prefetching tiles at
-// 256^3 FP32 0.74 vs 0.475, FP16 0.62 vs 0.29; 384x2 prefetching tiles at 384^2 x 192 FP32
-// 1.02 vs 0.94, FP16 0.95 vs 0.64. 1 where not measured (uniform chunks).
-inline double walled_plane_cost(int cfg, int elem) {
-    if (cfg == 3) return elem == 2 ? 2.0 : 1.5;
-    if (cfg == 8) return elem == 2 ? 1.5 : 1.0;
-    return 1.0;
-}
-
-// Layout of a single lattice's fused step from its uniform chunk depth zc. With walls along z
-// only (2- and 4-byte storage) the walled end chunks, which run the general form, are made
-// shorter and the interior ones, which run the solid-free form, longer, with the chunk count
-// unchanged, so that the workgroups of the walled and of the interior chunks (on different
-// XCDs: tiles are mapped to XCDs in contiguous ranges) have about the same work.
-inline ZChunks fused_zchunks(const lbm_params& p, int elem, int cfg, int zc) {
-    const ZChunks u = zchunks_of(p.nz, zc, zc);
-    if (!solid_free_enabled() || elem == 8 || !z_walls_only(p)) return u;
-    const bool lo = p.bc[2][0] == LBM_BC_WALL, hi = p.bc[2][1] == LBM_BC_WALL;
-    const int nb = (lo ? 1 : 0) + (hi ? 1 : 0), n = u.n, nz = p.nz;
-    const double w = walled_plane_cost(cfg, elem);
-    if (n - nb < 1 || w <= 1.0) return u;
-    const int i = (int)std::lround(nz / (nb / w + (n - nb)));
-    const int b = nz - (n - nb) * i;                       // planes of the walled chunks
-    const int blo = nb == 2 ? (b + 1) / 2 : b, bhi = nb == 2 ? b / 2 : b;
-    // a walled chunk must hold the wall plane and the two planes next to it, and fit in one
-    if (i < 1 || (lo && (blo < 3 || blo > i)) || (hi && (bhi < 3 || bhi > i))) return u;
-    const ZChunks z = zchunks_of(nz, lo ? blo : i, i);
-    return z.n == n ? z : u;
-}
-
-// Layout of a lattice in a batched step (many workgroups per CU, so no balancing): with a
-// wall at z = 0 the first chunk holds only the 4 planes next to it.
-inline ZChunks batch_zchunks(const lbm_params& p, int zc) {
-    if (!solid_free_enabled() || p.storage == LBM_FP64 || !z_walls_only(p) ||
-        p.bc[2][0] != LBM_BC_WALL || p.nz < 4 + zc)
-        return zchunks_of(p.nz, zc, zc);
-    return zchunks_of(p.nz, 4, zc);
-}
-
-// Chunks (bit iz, chunks 0..63) of layout zk whose planes z0 - 2 .. z1 + 1 (periodic) hold no
-// solid node. Walls along x or y put solid nodes in every plane; a wall along z is the plane 0
-// or nz - 1; a cylinder along x fills the planes cyl_z - cyl_r .. cyl_z + cyl_r (taken one
-// plane wider either side).
-inline uint64_t solid_free_chunks(const lbm_params& p, const ZChunks& zk) {
-    if (!solid_free_enabled()) return 0;
-    for (int a = 0; a < 2; ++a)
-        if (p.bc[a][0] == LBM_BC_WALL || p.bc[a][1] == LBM_BC_WALL) return 0;
-    const int nz = p.nz;
-    auto solid_plane = [&](int z) {
-        z = ((z % nz) + nz) % nz;
-        if (p.bc[2][0] == LBM_BC_WALL && z == 0) return true;
-        if (p.bc[2][1] == LBM_BC_WALL && z == nz - 1) return true;
-        if (p.cylinder && z >= std::floor(p.cyl_z - p.cyl_r) - 1 && z <= std::ceil(p.cyl_z + p.cyl_r) + 1)
-            return true;
-        return false;
-    };
-    uint64_t m = 0;
-    for (int iz = 0; iz < zk.n && iz < 64; ++iz) {
-        const int z0 = iz == 0 ? 0 : zk.zlo + (iz - 1) * zk.zc;
-        const int z1 = std::min(zk.zlo + iz * zk.zc, nz);
-        bool free = true;
-        for (int z = z0 - 2; z <= z1 + 1 && free; ++z) free = !solid_plane(z);
-        if (free) m |= 1ull << iz;
-    }
-    return m;
-}
 
 // Planes per z-chunk, tile order and cache hints of a launch (defaults of fused.h, then the
 // LBM_FUSED_* tuning overrides), and the workgroup count.
-struct FusedPlan { int zc, zlo, remap, hints; long long workgroups; };
+struct FusedPlan { int zc, remap, hints; long long workgroups; };
 inline FusedPlan fused_plan(const lbm_params& p, int elem, int cfg, int cus) {
     const FusedCfg& f = kFusedCfgs[cfg];
     const long long tiles = (long long)((p.nx + f.tx - 1) / f.tx) * ((p.ny + f.ty - 1) / f.ty);
@@ -256,19 +203,13 @@ inline FusedPlan fused_plan(const lbm_params& p, int elem, int cfg, int cus) {
     if (const char* e = getenv("LBM_FUSED_ZC")) pl.zc = std::max(1, atoi(e));   // tuning override
     if (const char* e = getenv("LBM_FUSED_REMAP")) pl.remap = atoi(e) != 0;    // tuning override
     pl.zc = std::min(pl.zc, p.nz);
-    const ZChunks zk = fused_zchunks(p, elem, cfg, pl.zc);
-    pl.zc = zk.zc;
-    pl.zlo = zk.zlo;
-    pl.workgroups = tiles * zk.n;
+    pl.workgroups = tiles * ((p.nz + pl.zc - 1) / pl.zc);
     return pl;
 }
 
-inline void fused_chunking(const lbm_ctx* c, int& zc, int& remap, int& hints, int& zlo,
-                           int& nchunks) {
+inline void fused_chunking(const lbm_ctx* c, int& zc, int& remap, int& hints) {
     const FusedPlan pl = fused_plan(c->p, (int)c->elem, c->fused_cfg, c->cus);
     zc = pl.zc;
-    zlo = pl.zlo;
-    nchunks = zchunks_of(c->p.nz, pl.zlo, pl.zc).n;
     remap = pl.remap;
     hints = pl.hints;
 }

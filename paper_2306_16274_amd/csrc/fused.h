@@ -30,6 +30,8 @@
 // outside the domain compute psi of the wrapped node but never store.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace lbmk {
@@ -134,8 +136,9 @@ constexpr int default_fused_hints(const FusedCfg& c, int elem_bytes) {
 // spills; FP16 28.1 vs 21.5); FP64 takes 64x4 tiles (32x8: 12.3-12.7 vs 9.4 at 384^2 x 160,
 // 6.7-7.1 vs 5.4-5.6 for D3Q27 at 320 x 256 x 192: 640 or 768 threads leave too few VGPRs).
 // D3Q27 on a solid mask at width 320 (the cylinder workload, 320 x 256 x 192, walls and a
-// cylinder with wetting): prefetching 320x2 tiles, FP32 1.02 vs 1.22-1.26 ms plain, FP16 0.92
-// vs 0.99-1.03 (the masked form holds 161 VGPRs without spills; between plain walls it spills).
+// cylinder with wetting): prefetching 320x2 tiles, FP32 0.90 vs 0.98 ms plain, FP16 0.80 vs
+// 0.78 with the solid-free segments (1.02 vs 1.22-1.26 and 0.92 vs 0.99-1.03 without them);
+// the masked form holds 161 VGPRs without spills, between plain walls it spills.
 constexpr int default_fused_cfg_index(int nx, int elem_bytes, int Q, bool mask = false) {
     return (nx == 320 || nx == 384)
                ? (elem_bytes == 8 ? 9
@@ -249,16 +252,8 @@ __device__ __forceinline__ R sum_q(const R* v) {
     return s;
 }
 
-// Planes z0 .. z1 - 1 of z-chunk iz: chunk 0 holds g.zlo planes (zc when g.zlo is 0), the
-// others zc, the last the rest.
-__device__ __forceinline__ void chunk_range(const Grid& g, int iz, int zc, int& z0, int& z1) {
-    const int zl = g.zlo > 0 ? g.zlo : zc;
-    z0 = iz == 0 ? 0 : zl + (iz - 1) * zc;
-    z1 = min(zl + iz * zc, g.nz);
-}
-
 // LDS of one tile shape, shared by the geometry forms of that shape: a kernel that runs the
-// solid-free form of its tile on some z-chunks (see solid_free) then holds one copy of the
+// solid-free form of its tile on some planes (fused_segments) then holds one copy of the
 // tile's buffers, not one per form.
 template <typename R, int LY, int LX>
 struct RingLds { R ring[4][LY][LX]; };
@@ -279,48 +274,61 @@ __device__ __forceinline__ PfLds<S, Q, LY, LX, NT, H>& pf_lds() {
     return s;
 }
 
-// solid_free: bit iz is set when z-chunk iz (planes z0 .. z1-1) and the two planes either
-// side of it hold no solid node (computed on the host from the walls and the cylinder).
-// Every node such a chunk collides then has only fluid nodes within two planes, so the pulls
-// need no bounce-back, every psi it reads is a fluid node's, and the solid and wetting terms
-// vanish: the form of the tile for a lattice without solid nodes gives the same values for
-// those nodes (up to the sign of exact zeros). Walled and cylinder lattices of 2- and 4-byte
-// storage run that form on such chunks; FP64 tiles always take the general form.
-template <typename T, int GEOM>
-__device__ __forceinline__ bool run_solid_free(uint64_t solid_free, int iz) {
-    if constexpr (GEOM == GEOM_NONE || sizeof(T) == 8) return false;
-    else return iz < 64 && ((solid_free >> iz) & 1ull) != 0;
+// Solid-free form. A walled or cylinder lattice runs the general form of its tile, with
+// bounce-back in the pulls, solid tests and wetting sums over the neighbours and the mirror
+// reading of psi at solid ones. Only planes within two of a solid node need it: a plane z
+// whose planes z - 2 .. z + 2 hold no solid node pulls without bounce-back, reads the psi of
+// fluid nodes only (its own and, through its ring, planes z - 1 .. z + 1, each from pulls
+// within one more plane) and has no solid or wetting terms, so the form of the tile for a
+// lattice without solid nodes gives its nodes the same values (up to the sign of exact
+// zeros). The host gives the longest run of such planes as [g.sf0, g.sf1); a workgroup splits
+// its chunk into a general and a solid-free segment, each marched like a chunk of its own
+// (with its two lead-in planes), a barrier between them so that the ring and the prefetch
+// buffers are free again. 2- and 4-byte storage only; FP64 tiles always take the general
+// form.
+template <typename T, int GEOM, typename F>
+__device__ __forceinline__ void fused_segments(const Grid& g, int z0, int z1, F&& run) {
+    if constexpr (GEOM == GEOM_NONE || sizeof(T) == 8) {
+        run(std::integral_constant<int, GEOM>{}, z0, z1);
+    } else {
+        // one general segment and one solid-free segment at most, one call site each (a
+        // chunk that would need general segments on both sides runs wholly in the general
+        // form): segments are independent, so the general one runs first
+        int glo = z0, ghi = z1, flo = z1, fhi = z1;
+        const int a = max(z0, g.sf0), b = min(z1, g.sf1);
+        if (a < b && (a == z0 || b == z1)) {
+            flo = a;
+            fhi = b;
+            glo = a == z0 ? b : z0;
+            ghi = a == z0 ? z1 : a;
+        }
+        if (glo < ghi) run(std::integral_constant<int, GEOM>{}, glo, ghi);
+        if (flo < fhi) {
+            if (glo < ghi) __syncthreads();
+            run(std::integral_constant<int, GEOM_NONE>{}, flo, fhi);
+        }
+    }
 }
 
 // FULLX: the tile spans the whole x extent (TX == nx); x wraps inside the tile and the
 // halo is just the rows y0-1 and y0+TY (H = 2 TX, one halo node per thread when TY = 2).
-// One tile (workgroup) of the fused step: tile index t of a domain with ntx x nty tiles
-// per plane and z-chunks of zc planes. Shared by the single-domain kernel and the
-// multi-domain (batched) kernel.
+// Planes z0 .. z1 - 1 of tile (column) t of a domain with ntx x nty tiles per plane, in the
+// geometry form GEOM.
 template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX, bool NTS, bool WIDE = false>
-__device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restrict__ fout,
-                                           const uint32_t* __restrict__ links, const Grid& g,
-                                           const Phys<typename Arith<T>::type>& P,
-                                           int t, int ntx, int nty, int zc, int hints,
-                                           uint64_t solid_free = 0) {
+__device__ __forceinline__ void fused_tile_seg(const T* __restrict__ fin, T* __restrict__ fout,
+                                               const uint32_t* __restrict__ links, const Grid& g,
+                                               const Phys<typename Arith<T>::type>& P,
+                                               int t, int ntx, int nty, int z0, int z1, int hints) {
     using R = typename Arith<T>::type;
     constexpr int LX = FULLX ? TX : TX + 2, LY = TY + 2;
     constexpr int OX = FULLX ? 0 : 1;                 // LDS column of tile column 0
     constexpr int H = FULLX ? 2 * TX : 2 * (TX + TY) + 4;
     static_assert(H <= TX * TY, "halo larger than the workgroup");
-    if (run_solid_free<T, GEOM>(solid_free, t / (ntx * nty))) {
-        fused_tile<Q, T, GEOM_NONE, TX, TY, FULLX, NTS, WIDE>(fin, fout, links, g, P, t, ntx, nty,
-                                                              zc, hints);
-        return;
-    }
     auto& ring = ring_lds<R, LY, LX>().ring;
 
     const int ix = t % ntx; t /= ntx;
     const int iy = t % nty;
-    const int iz = t / nty;
     const int x0 = ix * TX, y0 = iy * TY;
-    int z0, z1;
-    chunk_range(g, iz, zc, z0, z1);
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
     const int x = x0 + lx, y = y0 + ly;
@@ -436,6 +444,22 @@ __device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restr
     }
 }
 
+// One tile (workgroup) of the fused step: tile index t of a domain with ntx x nty tiles
+// per plane and z-chunks of zc planes. Shared by the single-domain kernel and the
+// multi-domain (batched) kernel.
+template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX, bool NTS, bool WIDE = false>
+__device__ __forceinline__ void fused_tile(const T* __restrict__ fin, T* __restrict__ fout,
+                                           const uint32_t* __restrict__ links, const Grid& g,
+                                           const Phys<typename Arith<T>::type>& P,
+                                           int t, int ntx, int nty, int zc, int hints) {
+    const int z0 = t / (ntx * nty) * zc, z1 = min(z0 + zc, g.nz);
+    fused_segments<T, GEOM>(g, z0, z1, [&](auto form, int a, int b) {
+        fused_tile_seg<Q, T, decltype(form)::value, TX, TY, FULLX, NTS, WIDE>(fin, fout, links, g,
+                                                                             P, t, ntx, nty, a, b,
+                                                                             hints);
+    });
+}
+
 #define LBM_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
 
 // Wait until every vector memory operation of this wavefront has completed (vmcnt(0); the
@@ -511,10 +535,10 @@ __device__ __forceinline__ float pf_value<_Float16, float>(uint32_t v) {
 }
 
 template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX, bool NTS>
-__device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __restrict__ fout,
-                                              const uint32_t* __restrict__ links, const Grid& g,
-                                              const Phys<float>& P, int t, int ntx, int nty,
-                                              int zc, int hints, uint64_t solid_free = 0) {
+__device__ __forceinline__ void fused_tile_pf_seg(const T* __restrict__ fin, T* __restrict__ fout,
+                                                  const uint32_t* __restrict__ links, const Grid& g,
+                                                  const Phys<float>& P, int t, int ntx, int nty,
+                                                  int z0, int z1, int hints) {
     static_assert(sizeof(T) == 4 || sizeof(T) == 2, "the LDS prefetch moves 2- or 4-byte elements");
     using R = float;
     using S = typename PfSlot<T>::type;
@@ -525,11 +549,6 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
     static_assert(H <= NT && (!FULLX || TX % 64 == 0),
                   "halo larger than the tile, or full rows not whole wavefronts");
     static_assert(fused_pf_lds_bytes(Q, TX, TY, FULLX) <= kLdsBytesPerCU, "tile does not fit in LDS");
-    if (run_solid_free<T, GEOM>(solid_free, t / (ntx * nty))) {
-        fused_tile_pf<Q, T, GEOM_NONE, TX, TY, FULLX, NTS>(fin, fout, links, g, P, t, ntx, nty, zc,
-                                                           hints);
-        return;
-    }
     // the halo buffer holds H cells; the DMA of the last, partly used wavefront writes only
     // its active lanes
     auto& lds = pf_lds<S, Q, TY + 2, LX, NT, H>();
@@ -542,10 +561,7 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
 
     const int ix = t % ntx; t /= ntx;
     const int iy = t % nty;
-    const int iz = t / nty;
     const int x0 = ix * TX, y0 = iy * TY;
-    int z0, z1;
-    chunk_range(g, iz, zc, z0, z1);
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
     const int x = x0 + lx, y = y0 + ly;
@@ -743,6 +759,20 @@ __device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __re
     }
 }
 
+// One prefetching tile of the fused step (tile index t, z-chunks of zc planes), its chunk
+// split into geometry forms by fused_segments.
+template <int Q, typename T, int GEOM, int TX, int TY, bool FULLX, bool NTS>
+__device__ __forceinline__ void fused_tile_pf(const T* __restrict__ fin, T* __restrict__ fout,
+                                              const uint32_t* __restrict__ links, const Grid& g,
+                                              const Phys<float>& P, int t, int ntx, int nty,
+                                              int zc, int hints) {
+    const int z0 = t / (ntx * nty) * zc, z1 = min(z0 + zc, g.nz);
+    fused_segments<T, GEOM>(g, z0, z1, [&](auto form, int a, int b) {
+        fused_tile_pf_seg<Q, T, decltype(form)::value, TX, TY, FULLX, NTS>(fin, fout, links, g, P, t,
+                                                                          ntx, nty, a, b, hints);
+    });
+}
+
 // FP64 full-row tile with the own populations of plane z+2 prefetched into LDS (each double
 // as two dword DMAs into a low and a high slot array). The halo rows are pulled
 // synchronously, before the prefetch is issued: vector memory completes in order, so waiting
@@ -768,9 +798,8 @@ __device__ __forceinline__ void fused_tile_pf64(const double* __restrict__ fin,
 
     const int iy = t % nty;
     const int iz = t / nty;
-    const int y0 = iy * TY;
-    int z0, z1;
-    chunk_range(g, iz, zc, z0, z1);
+    const int y0 = iy * TY, z0 = iz * zc;
+    const int z1 = min(z0 + zc, g.nz);
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
     const int x = lx, y = y0 + ly;
@@ -910,11 +939,10 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_pf(const T* __restrict__
                                                           T* __restrict__ fout,
                                                           const uint32_t* __restrict__ links,
                                                           Grid g, Phys<float> P, int zc,
-                                                          int remap, int hints,
-                                                          uint64_t solid_free) {
+                                                          int remap, int hints) {
     const int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     fused_tile_pf<Q, T, GEOM, TX, TY, true, NTS>(fin, fout, links, g, P, t, 1,
-                                                 (g.ny + TY - 1) / TY, zc, hints, solid_free);
+                                                 (g.ny + TY - 1) / TY, zc, hints);
 }
 
 // Single domain. remap != 0: map workgroups to tiles so that each XCD gets a contiguous
@@ -925,10 +953,9 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused(const T* __restrict__ fi
                                                        const uint32_t* __restrict__ links,
                                                        Grid g, Phys<typename Arith<T>::type> P,
                                                        int ntx, int nty, int zc, int remap,
-                                                       int hints, uint64_t solid_free) {
+                                                       int hints) {
     const int t = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    fused_tile<Q, T, GEOM, TX, TY, FULLX, NTS, WIDE>(fin, fout, links, g, P, t, ntx, nty, zc, hints,
-                                                     solid_free);
+    fused_tile<Q, T, GEOM, TX, TY, FULLX, NTS, WIDE>(fin, fout, links, g, P, t, ntx, nty, zc, hints);
 }
 
 // One domain of a batched step: its buffers, geometry, physics and the first workgroup
@@ -942,7 +969,6 @@ struct DomainDesc {
     Phys<typename Arith<T>::type> P;
     int ntx, nty, zc, block0;
     int rows;                  // rows per tile of the row-tile kernel (k_step_fused_batch_rows)
-    uint64_t solid_free;       // z-chunks without a solid node within two planes (fused_tile)
 };
 
 // Many independent lattices advanced by one launch: workgroup b (after the XCD-contiguous
@@ -959,7 +985,7 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_batch(const DomainDesc<T
     }
     const DomainDesc<T>& D = d[lo];
     fused_tile<Q, T, GEOM, TX, TY, false, NTS>(D.fin, D.fout, D.links, D.g, D.P, b - D.block0,
-                                               D.ntx, D.nty, D.zc, 0, D.solid_free);
+                                               D.ntx, D.nty, D.zc, 0);
 }
 
 // Batched step with prefetching tiles (4-byte storage): as k_step_fused_batch.
@@ -974,7 +1000,7 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_batch_pf(const DomainDes
     }
     const DomainDesc<T>& D = d[lo];
     fused_tile_pf<Q, T, GEOM, TX, TY, false, NTS>(D.fin, D.fout, D.links, D.g, D.P, b - D.block0,
-                                                  D.ntx, D.nty, D.zc, 0, D.solid_free);
+                                                  D.ntx, D.nty, D.zc, 0);
 }
 
 
@@ -988,18 +1014,14 @@ __global__ __launch_bounds__(TX * TY) void k_step_fused_batch_pf(const DomainDes
 // interior rows, whose lanes need not fill whole wavefronts here). The psi ring is flat:
 // (rows + 2) L <= NT + 2 L <= 2 NT cells per plane. Arithmetic per node as in fused_tile.
 template <int Q, typename T, int GEOM, int NT, bool NTS>
-__device__ __forceinline__ void fused_tile_rows(const T* __restrict__ fin, T* __restrict__ fout,
-                                                const uint32_t* __restrict__ links, const Grid& g,
-                                                const Phys<float>& P, int t, int rows, int nty,
-                                                int zc, uint64_t solid_free = 0) {
+__device__ __forceinline__ void fused_tile_rows_seg(const T* __restrict__ fin, T* __restrict__ fout,
+                                                    const uint32_t* __restrict__ links, const Grid& g,
+                                                    const Phys<float>& P, int t, int rows, int nty,
+                                                    int z0, int z1) {
     static_assert(sizeof(T) == 4 || sizeof(T) == 2, "the LDS prefetch moves 2- or 4-byte elements");
     static_assert(NT % 64 == 0, "whole wavefronts");
     using R = float;
     using S = typename PfSlot<T>::type;
-    if (run_solid_free<T, GEOM>(solid_free, t / nty)) {
-        fused_tile_rows<Q, T, GEOM_NONE, NT, NTS>(fin, fout, links, g, P, t, rows, nty, zc);
-        return;
-    }
     auto& lds = pf_lds<S, Q, 1, 2 * NT, NT, NT>();
     auto& ring_rows = lds.ring;
     auto& pf_own = lds.own;
@@ -1009,10 +1031,7 @@ __device__ __forceinline__ void fused_tile_rows(const T* __restrict__ fin, T* __
 
     const int L = g.nx;
     const int iy = t % nty;
-    const int iz = t / nty;
     const int y0 = iy * rows;
-    int z0, z1;
-    chunk_range(g, iz, zc, z0, z1);
     const int tid = threadIdx.x;
     // lanes without a node take node 0's column and row (valid addresses; never stored, and
     // they write no ring cell)
@@ -1186,6 +1205,20 @@ __device__ __forceinline__ void fused_tile_rows(const T* __restrict__ fin, T* __
     }
 }
 
+// One row tile of the batched step (tile index t, z-chunks of zc planes), its chunk split
+// into geometry forms by fused_segments.
+template <int Q, typename T, int GEOM, int NT, bool NTS>
+__device__ __forceinline__ void fused_tile_rows(const T* __restrict__ fin, T* __restrict__ fout,
+                                                const uint32_t* __restrict__ links, const Grid& g,
+                                                const Phys<float>& P, int t, int rows, int nty,
+                                                int zc) {
+    const int z0 = t / nty * zc, z1 = min(z0 + zc, g.nz);
+    fused_segments<T, GEOM>(g, z0, z1, [&](auto form, int a, int b) {
+        fused_tile_rows_seg<Q, T, decltype(form)::value, NT, NTS>(fin, fout, links, g, P, t, rows,
+                                                                 nty, a, b);
+    });
+}
+
 // Batched step with row tiles of run-time width (fused_tile_rows): as k_step_fused_batch.
 template <int Q, typename T, int GEOM, int NT, bool NTS>
 __global__ __launch_bounds__(NT) void k_step_fused_batch_rows(const DomainDesc<T>* __restrict__ d,
@@ -1198,7 +1231,7 @@ __global__ __launch_bounds__(NT) void k_step_fused_batch_rows(const DomainDesc<T
     }
     const DomainDesc<T>& D = d[lo];
     fused_tile_rows<Q, T, GEOM, NT, NTS>(D.fin, D.fout, D.links, D.g, D.P, b - D.block0, D.rows,
-                                         D.nty, D.zc, D.solid_free);
+                                         D.nty, D.zc);
 }
 
 }  // namespace lbmk

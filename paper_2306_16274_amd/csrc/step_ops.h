@@ -54,11 +54,9 @@ static void launch_fused_cfg(lbm_ctx* c, const void* fin, void* fout) {
     const Phys<R>& P = phys_of<R>(c);
     const int ntx = (c->p.nx + TX - 1) / TX, nty = (c->p.ny + TY - 1) / TY;
     const long long tiles = (long long)ntx * nty;
-    int zc, remap, hints, zlo, nchunks;
-    fused_chunking(c, zc, remap, hints, zlo, nchunks);
-    Grid g = grid_of(c);
-    g.zlo = zlo;
-    const uint64_t solid_free = solid_free_chunks(c->p, ZChunks{zlo, zc, nchunks});
+    int zc, remap, hints;
+    fused_chunking(c, zc, remap, hints);
+    const int nchunks = (c->p.nz + zc - 1) / zc;
     const dim3 grid((unsigned)(tiles * nchunks)), block(TX * TY);
     // 64-bit offsets are instantiated with plain stores only
     with_geom_nts(c, WIDE ? (hints & ~kHintNtStore) : hints, [&](auto geom, auto nts) {
@@ -66,7 +64,7 @@ static void launch_fused_cfg(lbm_ctx* c, const void* fin, void* fout) {
             hipLaunchKernelGGL((k_step_fused<Q, T, decltype(geom)::value, TX, TY, FULLX,
                                              decltype(nts)::value, WIDE>),
                                grid, block, 0, c->stream, (const T*)fin, (T*)fout, c->links,
-                               g, P, ntx, nty, zc, remap, hints, solid_free);
+                               grid_of(c), P, ntx, nty, zc, remap, hints);
     });
 }
 
@@ -77,32 +75,29 @@ template <int Q, typename T, int TX, int TY>
 static void launch_fused_pf(lbm_ctx* c, const void* fin, void* fout) {
     if constexpr (std::is_same<T, double>::value && fused_pf64_lds_bytes(Q, TX, TY) <= kLdsBytesPerCU) {
         const int nty = (c->p.ny + TY - 1) / TY;
-        int zc, remap, hints, zlo, nchunks;
-        fused_chunking(c, zc, remap, hints, zlo, nchunks);
-        Grid g = grid_of(c);
-        g.zlo = zlo;
+        int zc, remap, hints;
+        fused_chunking(c, zc, remap, hints);
+        const int nchunks = (c->p.nz + zc - 1) / zc;
         const dim3 grid((unsigned)(nty * nchunks)), block(TX * TY);
         const double* f0 = (const double*)fin;
         double* f1 = (double*)fout;
         with_geom_nts(c, hints, [&](auto geom, auto nts) {
             hipLaunchKernelGGL((k_step_fused_pf64<Q, decltype(geom)::value, TX, TY,
                                                   decltype(nts)::value>),
-                               grid, block, 0, c->stream, f0, f1, c->links, g, c->pd, zc,
+                               grid, block, 0, c->stream, f0, f1, c->links, grid_of(c), c->pd, zc,
                                remap, hints);
         });
     } else if constexpr ((sizeof(T) == 4 || sizeof(T) == 2) && fused_pf_lds_bytes(Q, TX, TY) <= kLdsBytesPerCU) {
         const int nty = (c->p.ny + TY - 1) / TY;
-        int zc, remap, hints, zlo, nchunks;
-        fused_chunking(c, zc, remap, hints, zlo, nchunks);
-        Grid g = grid_of(c);
-        g.zlo = zlo;
-        const uint64_t solid_free = solid_free_chunks(c->p, ZChunks{zlo, zc, nchunks});
+        int zc, remap, hints;
+        fused_chunking(c, zc, remap, hints);
+        const int nchunks = (c->p.nz + zc - 1) / zc;
         const dim3 grid((unsigned)(nty * nchunks)), block(TX * TY);
         with_geom_nts(c, hints, [&](auto geom, auto nts) {
             hipLaunchKernelGGL((k_step_fused_pf<Q, T, decltype(geom)::value, TX, TY,
                                                 decltype(nts)::value>),
                                grid, block, 0, c->stream, (const T*)fin, (T*)fout, c->links,
-                               g, c->pf, zc, remap, hints, solid_free);
+                               grid_of(c), c->pf, zc, remap, hints);
         });
     } else {
         launch_fused_cfg<Q, T, TX, TY, true>(c, fin, fout);

@@ -56,8 +56,7 @@ class lbm_params(ctypes.Structure):
 
 class lbm_fused_plan_t(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("config", "tile_x", "tile_y", "full_rows", "prefetch",
-                                               "z_chunk", "xcd_order", "hints", "addr64",
-                                               "z_first")] + [
+                                               "z_chunk", "xcd_order", "hints", "addr64")] + [
         ("workgroups", ctypes.c_int64)]
 
 

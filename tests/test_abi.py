@@ -169,11 +169,9 @@ def _plan_params(lbm, nx, ny, nz, geometry=None, storage=1, Q=19):
     # ... but on a cylinder mask the prefetching 320x2 tiles (FP32 and FP16)
     ((320, 256, 192, "cylinder"), 1, 27, dict(config=6, tile_x=320, prefetch=1, z_chunk=96)),
     ((320, 256, 192, "cylinder"), 2, 27, dict(config=6, prefetch=1)),
-    # between walls along z: shorter walled end chunks (the general form), longer interior
-    # ones (the solid-free form), one round of 256 workgroups
-    ((256, 256, 256, "zwalls"), 1, 19, dict(config=3, z_first=51, z_chunk=77, workgroups=256)),
-    ((256, 256, 256, "zwalls"), 2, 19, dict(config=3, z_first=43, z_chunk=85, workgroups=256)),
-    ((256, 256, 256, "zwalls"), 0, 19, dict(config=1, z_first=128, z_chunk=128)),
+    # walls along z change nothing in the plan (the solid-free planes are split off inside
+    # each workgroup's chunk)
+    ((256, 256, 256, "zwalls"), 1, 19, dict(config=3, z_chunk=64, workgroups=256)),
     # other widths: 64x8 tiles for 4-byte storage, 64x4 otherwise, 16-plane chunks
     ((300, 300, 250), 1, 19, dict(config=10, tile_x=64, tile_y=8, full_rows=0, z_chunk=16, hints=0)),
     ((300, 300, 250), 2, 27, dict(config=9, tile_x=64, tile_y=4, z_chunk=16)),
