@@ -134,6 +134,30 @@ def test_row_tiles_on_extreme_widths(L, monkeypatch):
         lat.close()
 
 
+@pytest.mark.parametrize("variant", ["rows", "tiles64x4"])
+def test_batch_solid_free_segments_equal_general_form(L, monkeypatch, variant):
+    """The batched step splits each member's z-chunks into general and solid-free segments
+    (planes with no solid node within two): with LBM_SOLID_FREE on and off the members' FP32
+    populations after one batch run of 8 steps are equal (np.array_equal), on the row tiles
+    and on the 64x4 tiles."""
+    monkeypatch.setenv("LBM_BATCH_ROWS", "1" if variant == "rows" else "0")
+    out = {}
+    for on in ("1", "0"):
+        monkeypatch.setenv("LBM_SOLID_FREE", on)
+        lats = [_make(L, w, "fp32") for w in _members()]
+        b = L.lbm_batch_create([m.ctx for m in lats], 4)
+        try:
+            L.lbm_batch_run(b, 2)
+        finally:
+            L.lbm_batch_destroy(b)
+        out[on] = [lat.get_populations() for lat in lats]
+        for lat in lats:
+            lat.close()
+    for w, a, g in zip(_members(), out["1"], out["0"]):
+        print(f"{variant} {w.name}: max |solid-free - general| = {float(np.max(np.abs(a - g))):.3e}")
+        assert np.array_equal(a, g), w.name
+
+
 def test_serving_results_same_alone_and_in_the_mix(L):
     """A compressed trace of 8 impact requests through the continuous-batching loop and
     through the one-at-a-time loop (same FP32 storage): every request's result (spreading
