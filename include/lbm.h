@@ -156,9 +156,13 @@ lbm_status lbm_get_populations(lbm_ctx* c, double* f);
    The launch configuration of the fused step (tile shape: full rows for nx = 256, 320 or
    384, else 64x8 or 64x4 tiles; z-chunk length; nontemporal hints) is chosen from the
    domain width, the storage type and the lattice; a population buffer of 4 GiB or more
-   takes 64x8 (4-byte storage) or 64x4 tiles with 64-bit offsets and plain stores. For tuning, the environment variables
-   LBM_FUSED_CONFIG, LBM_FUSED_ZC, LBM_FUSED_REMAP and LBM_FUSED_HINTS override it; every
-   configuration gives bitwise the same populations.                                   */
+   takes 64x8 (4-byte storage) or 64x4 tiles with 64-bit offsets and plain stores. On
+   walled and cylinder lattices with 2- or 4-byte storage, the planes with no solid node
+   within two planes run the arithmetic of a lattice without solid nodes (the same values
+   for those nodes). For tuning, the environment variables LBM_FUSED_CONFIG, LBM_FUSED_ZC,
+   LBM_FUSED_REMAP, LBM_FUSED_HINTS and LBM_SOLID_FREE (0: no solid-free planes) override
+   this; every configuration gives the same populations (bitwise, up to the sign of exact
+   zeros).                                                                              */
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps);
 
 /* Number of time steps taken since the last initialisation.                           */
