@@ -258,6 +258,10 @@ typedef struct {
     int32_t xcd_order;    /* 1: tiles mapped to XCDs in contiguous ranges (LBM_FUSED_REMAP) */
     int32_t hints;        /* bit 0: nontemporal stores; bit 1: nontemporal interior loads  */
     int32_t addr64;       /* 1: 64-bit byte offsets (population buffer of 4 GiB or more)    */
+    int32_t solid_free_lo; /* planes solid_free_lo .. solid_free_hi - 1 of a walled or      */
+    int32_t solid_free_hi; /* cylinder lattice run the arithmetic of a lattice without solid
+                              nodes (2- and 4-byte storage; LBM_SOLID_FREE); both 0 for FP64,
+                              for lattices without solid nodes and where no plane qualifies */
     int64_t workgroups;   /* workgroups of one time step                                    */
 } lbm_fused_plan_t;
 lbm_status lbm_fused_plan(const lbm_params* p, int32_t cus, lbm_fused_plan_t* out);

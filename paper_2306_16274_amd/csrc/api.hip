@@ -439,6 +439,13 @@ extern "C" lbm_status lbm_fused_plan(const lbm_params* p, int32_t cus, lbm_fused
     out->xcd_order = pl.remap;
     out->hints = addr64 ? (pl.hints & ~kHintNtStore) : pl.hints;
     out->addr64 = addr64 ? 1 : 0;
+    int sf0 = 0, sf1 = 0;
+    bool any_solid = p->cylinder != 0;
+    for (int a = 0; a < 3; ++a)
+        any_solid = any_solid || p->bc[a][0] == LBM_BC_WALL || p->bc[a][1] == LBM_BC_WALL;
+    if (elem != 8 && any_solid) solid_free_range(*p, sf0, sf1);
+    out->solid_free_lo = sf0;
+    out->solid_free_hi = sf1;
     out->workgroups = pl.workgroups;
     return LBM_OK;
 }

@@ -56,7 +56,8 @@ class lbm_params(ctypes.Structure):
 
 class lbm_fused_plan_t(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("config", "tile_x", "tile_y", "full_rows", "prefetch",
-                                               "z_chunk", "xcd_order", "hints", "addr64")] + [
+                                               "z_chunk", "xcd_order", "hints", "addr64",
+                                               "solid_free_lo", "solid_free_hi")] + [
         ("workgroups", ctypes.c_int64)]
 
 

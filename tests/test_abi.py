@@ -192,6 +192,41 @@ def test_fused_launch_plan(monkeypatch, shape, storage, Q, expect):
         assert plan[k] == v, (k, plan)
 
 
+@pytest.mark.parametrize("shape,geometry,storage,expect", [
+    # walls at z = 0 and nz - 1: planes 3 .. nz - 4 have no solid node within two planes
+    ((256, 256, 256), "zwalls", 1, (3, 253)),
+    ((384, 384, 192), "zwalls", 2, (3, 189)),
+    # a wall at z = 0 only (periodic above): the run stops two planes short of the wrap
+    ((256, 4, 40), "zlo", 1, (3, 38)),
+    # the cylinder workload: cylinder (radius 20 at z = 20, taken as planes -1 .. 41) and walls
+    ((320, 256, 192), "cylinder_workload", 1, (44, 189)),
+    # walls along y leave no plane; FP64 never runs the solid-free form; no solid node: 0, 0
+    ((256, 256, 256), "ywalls", 1, (0, 0)),
+    ((256, 256, 256), "zwalls", 0, (0, 0)),
+    ((256, 256, 256), None, 1, (0, 0)),
+])
+def test_fused_plan_solid_free_planes(monkeypatch, shape, geometry, storage, expect):
+    """The planes a walled or cylinder lattice runs in the solid-free form (host-only plan)."""
+    from paper_2306_16274_amd import lbm
+    monkeypatch.delenv("LBM_SOLID_FREE", raising=False)
+    p = _plan_params(lbm, *shape, storage=storage)
+    if geometry == "zwalls":
+        p.bc[2][0] = p.bc[2][1] = lbm.LBM_BC_WALL
+    elif geometry == "zlo":
+        p.bc[2][0] = lbm.LBM_BC_WALL
+    elif geometry == "ywalls":
+        p.bc[1][0] = p.bc[1][1] = lbm.LBM_BC_WALL
+    elif geometry == "cylinder_workload":
+        p.lattice = 27
+        p.bc[2][0] = p.bc[2][1] = lbm.LBM_BC_WALL
+        p.cylinder, p.cyl_y, p.cyl_z, p.cyl_r = 1, 128.0, 20.0, 20.0
+    plan = lbm.lbm_fused_plan(p)
+    assert (plan["solid_free_lo"], plan["solid_free_hi"]) == expect, plan
+    monkeypatch.setenv("LBM_SOLID_FREE", "0")
+    plan = lbm.lbm_fused_plan(p)
+    assert (plan["solid_free_lo"], plan["solid_free_hi"]) == (0, 0)
+
+
 def test_fused_launch_plan_overrides_and_errors(monkeypatch):
     from paper_2306_16274_amd import lbm
     p = _plan_params(lbm, 256, 256, 256)
