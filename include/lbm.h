@@ -271,11 +271,11 @@ lbm_status lbm_fused_plan(const lbm_params* p, int32_t cus, lbm_fused_plan_t* ou
  * contexts (D3Q19, all FP32 or all FP64 storage, each initialised) and advances all of
  * them together: one kernel launch per time step covers the tiles of every member, and
  * steps_per_launch consecutive launches are captured once into a HIP graph. Each member
- * takes exactly the time step of lbm_step (bitwise the same populations: the per-node
- * arithmetic is shared). The batched step runs through 16-plane z-chunks: FP32 batches
- * whose members are at most 384 nodes wide on row tiles (768 threads covering as many
- * whole rows of a member as fit, each row wrapping in x, the next plane prefetched into
- * LDS), others on 64x4 tiles; nontemporal stores when every member's rows are whole
+ * takes exactly the time step of lbm_step (the same populations: the per-node arithmetic
+ * is shared). FP32 batches whose members are at most 384 nodes wide run row tiles (768
+ * threads covering as many whole rows of a member as fit, each row wrapping in x, the next
+ * plane prefetched into LDS) through 12-plane z-chunks, others 64x4 tiles through 16-plane
+ * z-chunks; nontemporal stores when every member's rows are whole
  * 128-byte lines; workgroups mapped to XCDs in contiguous ranges. LBM_BATCH_ROWS,
  * LBM_BATCH_TILE, LBM_BATCH_ZC, LBM_BATCH_PF, LBM_BATCH_NT and LBM_BATCH_REMAP override
  * this for tuning.

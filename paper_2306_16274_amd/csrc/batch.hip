@@ -14,6 +14,11 @@
 // Tile shapes of the batched kernel (index lbm_batch::tile) and the z-chunk depth.
 constexpr int kBatchTiles[2][2] = {{64, 4}, {32, 8}};
 constexpr int kBatchZC = 16;
+// z-chunk depth of the row tiles: with the solid-free segments 12-plane chunks beat 16 on
+// serving mixes (GLUPS, two runs each; 24 mixed sizes 28.0-28.2 vs 27.7-27.8, 8 x 128^3
+// 30.2-30.8 vs 30.1-30.5, 32 x 64^3 30.3-30.7 vs 29.8-30.2, 2 x 192^3 31.7-31.9 vs
+// 30.3-30.4; 8, 10, 14, 24 and 32 no better overall).
+constexpr int kRowsZC = 12;
 // Row tiles (k_step_fused_batch_rows): threads per workgroup (12 wavefronts: the walled
 // kernel fits the 168 VGPRs that leaves); members up to kRowsNT / 2
 // wide, 4-byte storage.
@@ -114,7 +119,7 @@ static lbm_status build_tables(lbm_batch* b) {
         const int rows = b->rows ? std::min(kRowsNT / c->p.nx, c->p.ny) : 0;
         const int ntx = b->rows ? 1 : (c->p.nx + TX - 1) / TX;
         const int nty = b->rows ? (c->p.ny + rows - 1) / rows : (c->p.ny + TY - 1) / TY;
-        int zc = kBatchZC;
+        int zc = b->rows ? kRowsZC : kBatchZC;
         if (const char* e = getenv("LBM_BATCH_ZC")) zc = std::max(1, atoi(e));    // tuning override
         zc = std::min(zc, c->p.nz);
         const long long nb = (long long)ntx * nty * ((c->p.nz + zc - 1) / zc);
