@@ -69,6 +69,10 @@ def make_params(w, storage, rho_ref, rho_v, rho_l, step_kernel="fused"):
     if w.rates == "unit":
         for k in ("s2b", "s3", "s3b", "s4", "s4b", "s5", "s6"):
             setattr(p, k, 1.0)
+    axes = {"x": 0, "y": 1, "z": 2}
+    for name in w.walls:                      # solid layers at index 0 / n - 1 of an axis
+        ax, side = name.split("_")
+        p.bc[axes[ax]][0 if side == "lo" else 1] = L.LBM_BC_WALL
     p.reduce_every = 0
     p.step_kernel = L.LBM_STEP_FUSED if step_kernel == "fused" else L.LBM_STEP_TWO_PASS
     return p
@@ -239,6 +243,9 @@ def main():
     ap.add_argument("--fp16-steps", type=int, default=100)
     ap.add_argument("--slab-steps", type=int, default=200,
                     help="steps on one GPU's z-slab of the workload shared by 8 GPUs (0: skip)")
+    ap.add_argument("--walls-steps", type=int, default=100,
+                    help="steps on the workload between walls at z = 0 and z = 255, with and "
+                         "without the solid-free planes (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=64,
                     help="requests of the time-compressed serving sweep (0: skip)")
@@ -278,6 +285,26 @@ def main():
                 "us_per_step": round(1000 * rs["ms_per_step"], 1),
                 "kernel_us": round(1000 * max(rs["kernel_ms"].values()), 1),
                 "steps": args.slab_steps, "storage": "fp32 shifted"}
+    # the same workload between walls at z = 0 and z = 255 (FP32 shifted): the planes two or
+    # more away from the walls run the solid-free form; beside it every plane in the general
+    # form (LBM_SOLID_FREE=0)
+    walls = None
+    if args.walls_steps > 0:
+        wz = w.with_(walls=("z_lo", "z_hi"))
+        rw = run_gpu(wz, "fp32", args.walls_steps, args.warmup, args.rho_ref, args.step_kernel)
+        os.environ["LBM_SOLID_FREE"] = "0"
+        try:
+            rg = run_gpu(wz, "fp32", args.walls_steps, args.warmup, args.rho_ref, args.step_kernel)
+        finally:
+            del os.environ["LBM_SOLID_FREE"]
+        walls = {"walls": "z = 0 and z = 255", "storage": "fp32 shifted",
+                 "value": round(rw["mlups"], 1), "unit": "MLUPS",
+                 "ms_per_step": round(rw["ms_per_step"], 4), "steps": args.walls_steps,
+                 "kernel_ms": rw["kernel_ms"],
+                 "solid_free_planes": [rw["plan"]["solid_free_lo"], rw["plan"]["solid_free_hi"]]
+                 if rw["plan"] else None,
+                 "general_form": {"value": round(rg["mlups"], 1),
+                                  "ms_per_step": round(rg["ms_per_step"], 4)}}
     serving_block = serving_sweep(args.serving_requests) if args.serving_requests > 0 else None
     copy_gbs = copy_bandwidth()
     stream_copy_gbs = L.lbm_copy_bandwidth()
@@ -326,6 +353,7 @@ def main():
                  "kernel_ms": r16["kernel_ms"]},
         "launch_plan": r32["plan"],
         "slab_of_8": slab,
+        "walls_z": walls,
         "effective_step_GBs": round(effective, 1),
         "effective_step_frac": round(effective / HBM_PEAK_GBS, 4),
         "kernel_ms": r32["kernel_ms"],
