@@ -230,3 +230,31 @@ def test_mirror_wall_is_a_symmetry_plane(Q):
     assert np.allclose(F[:, 1], Fm[:, 0], rtol=0, atol=1e-15)
     for k in Qab:
         assert np.allclose(Qab[k][1], Qm[k][0], rtol=0, atol=1e-15)
+
+
+@Q_BOTH
+def test_step_is_local_within_two_planes_of_a_wall(Q):
+    """One step reaches two lattice links (the pull: one; psi of the pulled neighbours for
+    F_int, F_ads and Q_ab: one more), so a node whose planes z - 2 .. z + 2 hold no solid
+    node updates exactly as in the same state without walls. Oracle with walls at z = 0 and
+    z = nz - 1 (wetting, kappa, the mirror reading of psi at the wall) against the periodic
+    oracle from the same random state: equal on planes 3 .. nz - 4, different on plane 2
+    (its pulls are fine, but psi of plane 1, which pulls from the wall, enters its force),
+    so the bound is tight."""
+    nx, ny, nz = 5, 4, 12
+    kw = dict(Q=Q, nx=nx, ny=ny, nz=nz, eos=eos.CarnahanStarling(0.5, 4, 1, 0.6), G_ads=0.2,
+              kappa=0.3, sigma=0.1)
+    Pw = lbm.Params(walls={"z_lo": True, "z_hi": True}, wall_psi="mirror", **kw)
+    Pp = lbm.Params(**kw)
+    rng = np.random.default_rng(21)
+    rho = rng.uniform(0.05, 0.4, Pw.shape)
+    u = rng.uniform(-0.02, 0.02, (3,) + Pw.shape)
+    solid = lbm.solid_mask(Pw)
+    fw = lbm.equilibrium_populations(Pw, rho, u, solid)
+    fp = lbm.equilibrium_populations(Pp, rho, u, np.zeros(Pp.shape, dtype=bool))
+    assert np.array_equal(fw[:, 1:nz - 1], fp[:, 1:nz - 1])
+    gw = lbm.step(fw, Pw, solid)
+    gp = lbm.step(fp, Pp)
+    inner = slice(3, nz - 3)
+    assert np.max(np.abs(gw[:, inner] - gp[:, inner])) == 0.0
+    assert np.max(np.abs(gw[:, 2] - gp[:, 2])) > 1e-8
