@@ -368,6 +368,7 @@ extern "C" lbm_status lbm_create(const lbm_params* pp, lbm_ctx** out) {
         CHK(hipGetLastError());
     }
     if (geom_of(c) == GEOM_MASK) CHK(build_links(c));
+    if (c->elem != 8 && c->any_solid) solid_free_range(c->p, c->sf0, c->sf1);
     CHK(dmalloc(c->stream, (void**)&c->dtot, 8 * sizeof(double)));
     CHK(hipHostMalloc((void**)&c->hhealth, 2 * sizeof(double), hipHostMallocDefault));
     CHK(hipEventCreateWithFlags(&c->health_ev, hipEventDisableTiming));

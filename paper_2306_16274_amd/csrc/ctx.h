@@ -30,6 +30,7 @@ struct lbm_ctx {
     void* psi = nullptr;           // float64 (FP64 storage) or float32
     uint8_t* solid = nullptr;
     uint32_t* links = nullptr;     // link words of the fused step (cylinder geometries)
+    int sf0 = 0, sf1 = 0;          // planes [sf0, sf1) run the solid-free form (solid_free_range)
     bool any_solid = false;
     double* mom = nullptr;         // rho, u (3), p: 5 N doubles, allocated on first use
     double* partial = nullptr;     // per-block partial sums (moments and health check)
@@ -144,7 +145,8 @@ inline Grid grid_of(const lbm_ctx* c) {
     Grid g;
     g.nx = c->p.nx; g.ny = c->p.ny; g.nz = c->p.nz; g.stride = c->stride;
     g.walls = 0;
-    solid_free_range(c->p, g.sf0, g.sf1);
+    g.sf0 = c->sf0;
+    g.sf1 = c->sf1;
     for (int a = 0; a < 3; ++a)
         for (int s = 0; s < 2; ++s)
             if (c->p.bc[a][s] == LBM_BC_WALL) g.walls |= 1 << (2 * a + s);
@@ -187,7 +189,6 @@ inline bool fused_prefetch_fits(const FusedCfg& f, int Q, int elem) {
     if (elem == 8) return fused_pf64_lds_bytes(Q, f.tx, f.ty) <= kLdsBytesPerCU;
     return fused_pf_lds_bytes(Q, f.tx, f.ty) <= kLdsBytesPerCU;
 }
-
 
 // Planes per z-chunk, tile order and cache hints of a launch (defaults of fused.h, then the
 // LBM_FUSED_* tuning overrides), and the workgroup count.
