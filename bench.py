@@ -292,11 +292,15 @@ def main():
     if args.walls_steps > 0:
         wz = w.with_(walls=("z_lo", "z_hi"))
         rw = run_gpu(wz, "fp32", args.walls_steps, args.warmup, args.rho_ref, args.step_kernel)
+        prev = os.environ.get("LBM_SOLID_FREE")
         os.environ["LBM_SOLID_FREE"] = "0"
         try:
             rg = run_gpu(wz, "fp32", args.walls_steps, args.warmup, args.rho_ref, args.step_kernel)
         finally:
-            del os.environ["LBM_SOLID_FREE"]
+            if prev is None:
+                del os.environ["LBM_SOLID_FREE"]
+            else:
+                os.environ["LBM_SOLID_FREE"] = prev
         walls = {"walls": "z = 0 and z = 255", "storage": "fp32 shifted",
                  "value": round(rw["mlups"], 1), "unit": "MLUPS",
                  "ms_per_step": round(rw["ms_per_step"], 4), "steps": args.walls_steps,
